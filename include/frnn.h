@@ -1,0 +1,131 @@
+/*
+ * frnn.h - C interface of the MI355X fixed-radius nearest-neighbour graph builder.
+ *
+ * The operation (paper, Section 2 "Description of the Exa.TrkX Pipeline": the
+ * graph built in the learned embedding space joins points that lie within a
+ * constant radius of each other; Section 3.4 "Fixed-Radius Nearest Neighbors":
+ * the points are projected to three coordinates and searched with a grid of
+ * cells).  For points X (n rows of d float32 coordinates), radius r and cap K:
+ *
+ *   r2      = fl32(r * r)
+ *   D(i,j)  = float32 sum over k = 0..d-1, in that order, of fl32(t_k * t_k),
+ *             t_k = fl32(X[i][k] - X[j][k]); every operation separately rounded,
+ *             no fused multiply-add, subnormals kept
+ *   N(i)    = { j != i : D(i,j) < r2 }
+ *   Out(i)  = N(i) if |N(i)| <= K, else its K members first in (D(i,j), j) order
+ *   edges   = { (i, j) : j in Out(i) }, i ascending then j ascending
+ *
+ * The result is unique, so two correct implementations produce identical bytes.
+ *
+ * Conventions shared by every entry point:
+ *   - Device pointers are HIP device allocations (for example PyTorch CUDA
+ *     tensors on ROCm); host pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     All device work is enqueued on it.  Inputs must stay alive and unchanged
+ *     until that work has finished.
+ *   - The caller owns every buffer.  The library allocates no device memory;
+ *     it keeps one small pinned host buffer per calling thread for results.
+ *   - Errors are returned as status codes; nothing is thrown across this
+ *     interface.  On any status other than FRNN_OK the output buffers hold
+ *     unspecified values.
+ *   - Calls on different streams may overlap if they use different workspaces.
+ */
+#ifndef FRNN_H
+#define FRNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum frnn_status {
+    FRNN_OK = 0,
+    FRNN_ERR_ARG = 1,         /* n < 0, d outside [3, 64], r not finite or <= 0, K outside
+                                 [1, FRNN_MAX_K], bad config, or a null pointer that is needed */
+    FRNN_ERR_NONFINITE = 2,   /* some coordinate is NaN or infinite; no edges are written */
+    FRNN_ERR_CAPACITY = 3,    /* more edges than edge_capacity; *n_edges holds the number needed */
+    FRNN_ERR_WORKSPACE = 4,   /* workspace smaller than frnn_workspace_bytes() */
+    FRNN_ERR_UNSUPPORTED = 5, /* n >= 2^31 */
+    FRNN_ERR_HIP = 6          /* a HIP runtime call failed */
+};
+
+#define FRNN_MAX_D 64
+#define FRNN_MAX_K 4096
+
+/* Tunables of the grid search.  They change speed only: every setting yields
+ * the same edges.  Zero-initialise and set what you need. */
+typedef struct frnn_config {
+    int32_t dims[3];   /* coordinates binned by the grid; all three must differ and lie in
+                          [0, d).  dims[0] is the fastest-varying cell axis.  Default (when
+                          dims[0] == dims[1]): the last three coordinates d-3, d-2, d-1,
+                          so the leading coordinates of the distance sum are unbinned. */
+    int32_t cell_div;  /* cell edge = r * (1 + 2^-10) / cell_div, cell_div in {1, 2, 3}
+                          (0 means 1).  Neighbours are searched cell_div cells away. */
+    int32_t tile;      /* query tile of the search kernel: 0 (default), 32 or 64 */
+    int32_t flags;     /* FRNN_FLAG_* bits */
+} frnn_config;
+
+/* frnn_config.flags: time every stage with HIP events on the call's stream and
+ * report the durations in frnn_stats.stage_ms (adds a few microseconds). */
+#define FRNN_FLAG_TIMING 1
+
+/* Stages reported in frnn_stats.stage_ms. */
+enum frnn_stage {
+    FRNN_STAGE_BOUNDS = 0,   /* bounds of the binned coordinates, non-finite check */
+    FRNN_STAGE_KEYS = 1,     /* grid plan, cell keys, histogram */
+    FRNN_STAGE_CELLS = 2,    /* scan of the histogram */
+    FRNN_STAGE_SCATTER = 3,  /* rows copied into cell order */
+    FRNN_STAGE_SEARCH = 4,   /* neighbour-cell search */
+    FRNN_STAGE_LONG = 5,     /* long neighbour lists and the K cap */
+    FRNN_STAGE_OFFSETS = 6,  /* scan of kept counts */
+    FRNN_STAGE_PLACE = 7,    /* edges written in (i, j) order */
+    FRNN_STAGES = 8
+};
+
+/* Counts describing one call, for diagnostics and benchmarks. */
+typedef struct frnn_stats {
+    int64_t n_edges;            /* edges written (= *n_edges on success) */
+    int64_t candidates;         /* (query, candidate) pairs examined by the search */
+    int64_t n_cells;            /* cells of the grid */
+    int32_t grid[3];            /* cells per binned axis */
+    int32_t dims[3];            /* binned coordinates */
+    float cell[3];              /* cell edge per binned axis */
+    int32_t capped_queries;     /* queries with |N(i)| > K */
+    int32_t overflow_queries;   /* queries handled by the long-list path */
+    float stage_ms[FRNN_STAGES]; /* per-stage device time with FRNN_FLAG_TIMING, else 0 */
+} frnn_stats;
+
+/* Bytes of device workspace frnn_build needs for n points of dimension d and
+ * room for edge_capacity edges.  Host-only arithmetic; returns 0 for invalid
+ * arguments (n < 0, d outside [3, 64], edge_capacity < 0). */
+size_t frnn_workspace_bytes(int64_t n, int32_t d, int64_t edge_capacity);
+
+/* Builds the FRNN graph of the points.
+ *   points          device, float32, row-major [n, d] (row i at points + i*d)
+ *   n, d            point count (0 <= n < 2^31) and dimension (3 <= d <= 64)
+ *   r, K            radius (finite, > 0) and cap (1 <= K <= FRNN_MAX_K)
+ *   workspace       device scratch of at least frnn_workspace_bytes(n, d, edge_capacity)
+ *                   bytes, 256-byte aligned; its contents on entry do not matter
+ *   src, dst        device, int64 [edge_capacity] each: edge e is (src[e], dst[e]),
+ *                   src the query i, dst the neighbour j, sorted by (i, j)
+ *   n_edges         host: receives E, or the E needed when it returns FRNN_ERR_CAPACITY
+ *   config          host, may be NULL for defaults
+ *   stats           host, may be NULL
+ *   stream          hipStream_t as void*
+ * Blocks the calling thread until the edge count is known (one device-to-host
+ * copy at the end of the work enqueued on `stream`). */
+int frnn_build(const float *points, int64_t n, int32_t d, float r, int32_t K,
+               void *workspace, size_t workspace_bytes,
+               int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *n_edges,
+               const frnn_config *config, frnn_stats *stats, void *stream);
+
+/* Static name of a status code. */
+const char *frnn_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRNN_H */

@@ -1,0 +1,148 @@
+"""Parity of the HIP path with the CPU oracle: identical bytes, edge for edge.
+
+The edge list is unique (definition in include/frnn.h), so the bar is exact
+equality of the int64 [2, E] arrays.  Every case runs through the C interface
+via the ctypes binding.
+"""
+
+import functools
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import invariants, oracle
+from paper_2202_06929_amd import events, frnn
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_edges(X, r, K, **kw):
+    pts = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(DEV)
+    e = frnn.build(pts, r, K, **kw)
+    torch.cuda.synchronize()
+    return e.cpu().numpy()
+
+
+@functools.lru_cache(maxsize=None)
+def event_and_oracle(name):
+    spec = {"tiny": events.TINY, "single": events.SINGLE, "high": events.HIGH}[name]
+    X, _ = events.generate(spec)
+    return spec, X, oracle.frnn_grid(X, spec.r, spec.K)
+
+
+def assert_same(got, want):
+    assert got.dtype == np.int64 and want.dtype == np.int64
+    assert got.shape == want.shape, (got.shape, want.shape)
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero((got != want).any(0))[:5]
+        raise AssertionError(f"first differing edges at {bad.tolist()}: got {got[:, bad].T.tolist()} "
+                             f"want {want[:, bad].T.tolist()}")
+
+
+@pytest.mark.parametrize("name", ["tiny", "single", "high"])
+def test_workload_events_match_oracle(name):
+    spec, X, want = event_and_oracle(name)
+    log(f"parity {name}: n={spec.n} d={spec.d} r={spec.r} K={spec.K}")
+    got, st = frnn.build(torch.from_numpy(X).to(DEV), spec.r, spec.K, return_stats=True)
+    torch.cuda.synchronize()
+    assert_same(got.cpu().numpy(), want)
+    assert st["n_edges"] == want.shape[1]
+    assert st["capped_queries"] == 0
+
+
+@pytest.mark.parametrize("case", events.stress_cases(), ids=lambda c: c.name)
+def test_stress_cases_match_oracle(case):
+    log(f"stress {case.name}: n={len(case.points)} r={case.r} K={case.K}")
+    want = oracle.frnn_grid(case.points, case.r, case.K)
+    got = gpu_edges(case.points, case.r, case.K)
+    assert_same(got, want)
+
+
+@pytest.mark.parametrize("d", [3, 4, 5, 7, 8, 9, 12, 13, 16, 17, 24, 31, 48, 64])
+def test_every_dimension_bucket(d):
+    spec = events.EventSpec(n=3000, d=d, n_clusters=250, size_lo=5, size_hi=15, sigma=0.02,
+                            noise_frac=0.1, r=0.1 * max(1.0, (d / 8) ** 0.5), K=16, seed=100 + d)
+    X, _ = events.generate(spec)
+    log(f"dimension d={d}")
+    assert_same(gpu_edges(X, spec.r, spec.K), oracle.frnn_grid(X, spec.r, spec.K))
+
+
+@pytest.mark.parametrize("cfg", [
+    frnn.Config(), frnn.Config(dims=(0, 1, 2)), frnn.Config(dims=(2, 0, 5)),
+    frnn.Config(cell_div=2), frnn.Config(cell_div=3), frnn.Config(dims=(0, 1, 2), cell_div=2),
+], ids=["default", "lead_dims", "mixed_dims", "div2", "div3", "lead_div2"])
+@pytest.mark.parametrize("name", ["tiny", "single"])
+def test_every_config_gives_the_same_edges(cfg, name):
+    spec, X, want = event_and_oracle(name)
+    log(f"config {cfg} on {name}")
+    assert_same(gpu_edges(X, spec.r, spec.K, config=cfg), want)
+
+
+def test_repeated_runs_are_identical():
+    spec, X, want = event_and_oracle("single")
+    pts = torch.from_numpy(X).to(DEV)
+    first = frnn.build(pts, spec.r, spec.K).cpu().numpy()
+    for _ in range(9):
+        assert np.array_equal(frnn.build(pts, spec.r, spec.K).cpu().numpy(), first)
+    assert_same(first, want)
+
+
+def test_capacity_error_reports_the_needed_count_and_retry_succeeds():
+    spec, X, want = event_and_oracle("tiny")
+    pts = torch.from_numpy(X).to(DEV)
+    n, d = X.shape
+    cap = 100
+    ws = torch.empty(frnn.workspace_bytes(n, d, cap), dtype=torch.uint8, device=DEV)
+    out = torch.empty((2, cap), dtype=torch.int64, device=DEV)
+    st, E = frnn.build_into(pts, spec.r, spec.K, ws, out[0], out[1])
+    assert st == frnn.FRNN_ERR_CAPACITY and E == want.shape[1]
+    got = frnn.build(pts, spec.r, spec.K, capacity=100)  # retries once with the exact count
+    assert_same(got.cpu().numpy(), want)
+    exact = frnn.build(pts, spec.r, spec.K, capacity=E)
+    assert exact.is_contiguous()
+    assert_same(exact.cpu().numpy(), want)
+
+
+def test_non_finite_input_is_rejected():
+    X, _ = events.generate(events.TINY)
+    for bad in (np.nan, np.inf, -np.inf):
+        Y = X.copy()
+        Y[777, 5] = bad
+        with pytest.raises(frnn.FrnnError) as e:
+            gpu_edges(Y, 0.1, 64)
+        assert e.value.status == frnn.FRNN_ERR_NONFINITE
+    # a good call right after an error still works
+    assert_same(gpu_edges(X, 0.1, 64), event_and_oracle("tiny")[2])
+
+
+def test_dyadic_exact_points():
+    X, _ = events.dyadic_event(5000, 8, 9)
+    assert_same(gpu_edges(X, 0.2, 64), oracle.frnn_grid(X, 0.2, 64))
+
+
+def test_ragged_sizes_and_small_events():
+    rng = np.random.Generator(np.random.PCG64(5))
+    for n in (1, 2, 3, 63, 64, 65, 255, 256, 257, 4095, 4096, 4097, 9001):
+        X = rng.uniform(-0.3, 0.3, size=(n, 6)).astype(np.float32)
+        log(f"ragged n={n}")
+        assert_same(gpu_edges(X, 0.15, 20), oracle.frnn_grid(X, 0.15, 20))
+
+
+def test_invariants_on_the_high_occupancy_event():
+    spec, X, want = event_and_oracle("high")
+    got = gpu_edges(X, spec.r, spec.K)
+    sample = np.random.Generator(np.random.PCG64(0)).choice(got.shape[1], 20000, replace=False)
+    D = oracle.pair_dist(X, got[0, sample], got[1, sample])
+    assert np.all(D < np.float32(spec.r) * np.float32(spec.r))
+    invariants.check(X[:0], spec.r, spec.K, np.zeros((2, 0), np.int64))
+    deg = np.bincount(got[0], minlength=spec.n)
+    assert deg.max() <= spec.K
