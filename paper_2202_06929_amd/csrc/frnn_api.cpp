@@ -6,6 +6,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "frnn.h"
 #include "frnn_internal.h"
 
@@ -53,6 +57,22 @@ bool config_ok(const frnn_config *c, int d) {
     return true;
 }
 
+// Resident search workgroups per (device, padded width), computed once.
+std::mutex g_blocks_mu;
+std::map<std::pair<int, int>, int> g_blocks;
+
+int search_blocks_cached(int dpad) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> lock(g_blocks_mu);
+    auto it = g_blocks.find({dev, dpad});
+    if (it != g_blocks.end()) return it->second;
+    int b = search_blocks_for(dpad);
+    if (b > kMaxSearchBlocks) b = kMaxSearchBlocks;
+    g_blocks[{dev, dpad}] = b;
+    return b;
+}
+
 thread_local Report *t_report = nullptr;  // pinned host copy of the device report
 thread_local hipEvent_t t_events[FRNN_STAGES + 1] = {};
 thread_local bool t_events_ready = false;
@@ -62,8 +82,8 @@ thread_local bool t_events_ready = false;
 Workspace layout(void *base, int64_t n, int d, int64_t edge_capacity) {
     const int dpad = dpad_for(d);
     const int64_t cells = cells_max_for(n);
-    const int64_t tiles_a = (cells + 1 + kScanTile - 1) / kScanTile;
-    const int64_t tiles_b = (n + 1 + kScanTile - 1) / kScanTile;
+    const int64_t tiles_cells = (cells + 1 + kScanTile - 1) / kScanTile;
+    const int64_t tiles_kept = (n + 1 + kScanTile - 1) / kScanTile;
     Carver cv{static_cast<char *>(base)};
     Workspace ws;
     ws.part = cv.take<BoundsPartial>(kBoundsBlocks);
@@ -74,14 +94,18 @@ Workspace layout(void *base, int64_t n, int d, int64_t edge_capacity) {
     ws.rank = cv.take<unsigned int>(n);
     ws.cell_count = cv.take<unsigned int>(cells);
     ws.cell_start = cv.take<unsigned int>(cells + 1);
-    ws.scan_sums = cv.take<unsigned long long>(tiles_a > tiles_b ? tiles_a : tiles_b);
+    ws.sums_cells = cv.take<unsigned long long>(tiles_cells);
+    ws.sums_kept = cv.take<unsigned long long>(tiles_kept);
     ws.sorted = cv.take<float>(static_cast<size_t>(n) * dpad);
     ws.sorted_id = cv.take<unsigned int>(n);
     ws.kept = cv.take<unsigned int>(n);
     ws.tpos = cv.take<unsigned long long>(n);
     ws.off = cv.take<long long>(n + 1);
     ws.heavy = cv.take<HeavyEntry>(n);
-    ws.temp = cv.take<unsigned int>(edge_capacity);
+    ws.temp = cv.take<unsigned int>(static_cast<size_t>(n) * kListCap + static_cast<size_t>(edge_capacity));
+    ws.tested = cv.take<unsigned long long>(kMaxSearchBlocks);
+    ws.tiles_cells_n = static_cast<int>(tiles_cells);
+    ws.tiles_kept_n = static_cast<int>(tiles_kept);
     ws.total_bytes = cv.at;
     return ws;
 }
@@ -147,6 +171,7 @@ extern "C" int frnn_build(const float *points, int64_t n, int32_t d, float r, in
     a.src = reinterpret_cast<long long *>(src);
     a.dst = reinterpret_cast<long long *>(dst);
     a.stream = static_cast<hipStream_t>(stream);
+    a.search_blocks = search_blocks_cached(a.dpad);
     const Workspace ws = layout(workspace, n, d, edge_capacity);
     const bool timing = config && (config->flags & FRNN_FLAG_TIMING);
     a.events = nullptr;

@@ -1,23 +1,23 @@
 // HIP kernels of the FRNN graph builder for CDNA4 (gfx950, wave64).
 //
-// Pipeline of one call (paper, Section 3.4: bin the projected points into grid
-// cells, then visit only the cells around each query):
-//   k_bounds      min/max of the three binned coordinates, non-finite check,
-//                 clears the cell histogram and counters
-//   k_keys        plan of the grid (cell edge, cells per axis), cell key of every
-//                 point, histogram with in-cell arrival rank
-//   k_tile_sums / k_scan_tiles
-//                 exclusive scan of the histogram -> first row of every cell
+// Pipeline of one call (paper, Section 3.4: bin the points by three projected
+// coordinates into grid cells, then visit only the cells around each query):
+//   k_bounds      min/max of the binned coordinates and a non-finite check over
+//                 all coordinates; clears the histogram, tile totals, counters
+//   k_keys        grid plan (cell edge, cells per axis), cell key of every point,
+//                 histogram with in-cell arrival rank, per-tile histogram totals
+//   k_scan_tiles  exclusive scan of the histogram -> first sorted row of each cell
 //   k_scatter     counting-sort scatter: rows copied into cell order
-//   k_search      one workgroup per cell: the queries of the cell against the
-//                 (2*reach+1)^2 contiguous x-runs of neighbouring cells, each lane
-//                 one candidate with its coordinates in registers, wave ballots
-//                 to collect hits into per-query lists in LDS, lists sorted and
-//                 stored in an unsorted edge store
-//   k_heavy       queries whose list overflowed LDS or exceeded K: exact K
-//                 smallest by (D, j) through an MSB-first radix select
+//   k_search      one wave per cell: the cell's queries against the (2R+1)^2
+//                 contiguous x-runs of neighbouring cells; each lane holds one
+//                 candidate row in registers, query rows are wave-uniform; an exact
+//                 early exit after the first three terms of the distance sum; wave
+//                 ballots collect hits; each list is sorted and stored
+//   k_heavy       per-tile kept totals; queries whose list is longer than the
+//                 search keeps, or longer than K: the K smallest by (D, j) found by
+//                 an MSB-first radix select
 //   k_scan_tiles  exclusive scan of kept counts -> int64 output offsets
-//   k_place       edges copied to their final (i asc, j asc) position
+//   k_place       edges written to their (i asc, j asc) positions, coalesced
 //
 // Distances follow one fixed order with every product and sum rounded on its
 // own: this file is compiled with -ffp-contract=off and the pragma below.
@@ -39,18 +39,34 @@ __device__ __forceinline__ unsigned int prefix_count(unsigned long long mask) {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
-// Squared distance of the definition: ascending coordinates, separately rounded.
-// Rows are zero-padded to DP coordinates; adding +0 leaves the sum unchanged.
-template <int DP>
-__device__ __forceinline__ float sq_dist(const float (&a)[DP], const float *b) {
-    float s = 0.0f;
+__device__ __forceinline__ unsigned int uniform(unsigned int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Orders the LDS accesses of one wave (lanes of a wave exchange data through LDS
+// without a workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Partial sum of the definition over coordinates [K0, K1): ascending order, every
+// product and sum rounded on its own.  Rows are zero-padded; adding +0 leaves a
+// sum unchanged, so padded rows give the same D as unpadded ones.  Partial sums of
+// non-negative terms never decrease, so s >= r2 after a prefix rejects exactly.
+template <int K0, int K1, int DP>
+__device__ __forceinline__ float add_terms(float s, const float (&a)[DP], const float *__restrict__ b) {
 #pragma unroll
-    for (int k = 0; k < DP; ++k) {
-        float t = a[k] - b[k];
-        float t2 = t * t;
+    for (int k = K0; k < K1; ++k) {
+        const float t = a[k] - b[k];
+        const float t2 = t * t;
         s = s + t2;
     }
     return s;
+}
+
+template <int DP>
+__device__ __forceinline__ float sq_dist(const float (&a)[DP], const float *__restrict__ b) {
+    return add_terms<0, DP, DP>(0.0f, a, b);
 }
 
 // Row `s` of the zero-padded sorted points (DP is a multiple of 4, rows 16-byte aligned).
@@ -93,7 +109,7 @@ __device__ unsigned long long block_sum(unsigned long long v, unsigned long long
     __syncthreads();
     unsigned long long t = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) t += scratch[w];
+    for (int w = 0; w < kWaves; ++w) t += scratch[w];
     __syncthreads();
     return t;
 }
@@ -111,55 +127,78 @@ __device__ unsigned long long block_exclusive_scan(unsigned long long v, unsigne
 
 // ------------------------------------------------------------------ bounds
 
+struct BoundsAcc {
+    float mn[3] = {INFINITY, INFINITY, INFINITY};
+    float mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    __device__ __forceinline__ void add(float v, int col, int d0, int d1, int d2) {
+        bad |= !__builtin_isfinite(v);
+        if (col == d0) { mn[0] = fminf(mn[0], v); mx[0] = fmaxf(mx[0], v); }
+        if (col == d1) { mn[1] = fminf(mn[1], v); mx[1] = fmaxf(mx[1], v); }
+        if (col == d2) { mn[2] = fminf(mn[2], v); mx[2] = fmaxf(mx[2], v); }
+    }
+};
+
 __global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ X, int n, int d,
-                                                   int d0, int d1, int d2,
+                                                   int d0, int d1, int d2, int vec4,
                                                    BoundsPartial *__restrict__ part,
-                                                   unsigned int *__restrict__ cell_count,
-                                                   int cells_max, Counters *__restrict__ ctr) {
+                                                   unsigned int *__restrict__ cell_count, int cells_max,
+                                                   unsigned long long *__restrict__ sums_cells, int tiles_cells,
+                                                   Counters *__restrict__ ctr) {
     const int tid = blockIdx.x * kBlock + threadIdx.x;
     const int stride = gridDim.x * kBlock;
     for (int c = tid; c < cells_max; c += stride) cell_count[c] = 0u;
+    for (int c = tid; c < tiles_cells; c += stride) sums_cells[c] = 0ull;
     if (tid == 0) {
-        ctr->temp_top = 0ull;
-        ctr->tested = 0ull;
-        ctr->heavy_count = 0u;
-        ctr->capped = 0u;
-        ctr->heavy_next = 0u;
+        Counters z = {};
+        *ctr = z;
     }
-    float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY;
-    float mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY;
-    int bad = 0;
-    for (int i = tid; i < n; i += stride) {
-        const float *row = X + static_cast<size_t>(i) * d;
-        for (int k = 0; k < d; ++k) bad |= !__builtin_isfinite(row[k]);
-        const float a = row[d0], b = row[d1], c = row[d2];
-        mn0 = fminf(mn0, a); mx0 = fmaxf(mx0, a);
-        mn1 = fminf(mn1, b); mx1 = fmaxf(mx1, b);
-        mn2 = fminf(mn2, c); mx2 = fmaxf(mx2, c);
+    BoundsAcc acc;
+    const long long total = static_cast<long long>(n) * d;
+    if (vec4) {
+        const float4 *X4 = reinterpret_cast<const float4 *>(X);
+        const long long nv = total / 4;
+        for (long long v = tid; v < nv; v += stride) {
+            const float4 x = X4[v];
+            int col = static_cast<int>((4 * v) % d);
+            acc.add(x.x, col, d0, d1, d2);
+            col = col + 1 == d ? 0 : col + 1;
+            acc.add(x.y, col, d0, d1, d2);
+            col = col + 1 == d ? 0 : col + 1;
+            acc.add(x.z, col, d0, d1, d2);
+            col = col + 1 == d ? 0 : col + 1;
+            acc.add(x.w, col, d0, d1, d2);
+        }
+    } else {
+        for (long long e = tid; e < total; e += stride) acc.add(X[e], static_cast<int>(e % d), d0, d1, d2);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        mn0 = fminf(mn0, __shfl_xor(mn0, o)); mx0 = fmaxf(mx0, __shfl_xor(mx0, o));
-        mn1 = fminf(mn1, __shfl_xor(mn1, o)); mx1 = fmaxf(mx1, __shfl_xor(mx1, o));
-        mn2 = fminf(mn2, __shfl_xor(mn2, o)); mx2 = fmaxf(mx2, __shfl_xor(mx2, o));
-        bad |= __shfl_xor(bad, o);
+        for (int p = 0; p < 3; ++p) {
+            acc.mn[p] = fminf(acc.mn[p], __shfl_xor(acc.mn[p], o));
+            acc.mx[p] = fmaxf(acc.mx[p], __shfl_xor(acc.mx[p], o));
+        }
+        acc.bad |= __shfl_xor(acc.bad, o);
     }
-    __shared__ BoundsPartial sp[kBlock / 64];
+    __shared__ BoundsPartial sp[kWaves];
     if (lane_id() == 0) {
         BoundsPartial &p = sp[wave_id()];
-        p.mn[0] = mn0; p.mn[1] = mn1; p.mn[2] = mn2;
-        p.mx[0] = mx0; p.mx[1] = mx1; p.mx[2] = mx2;
-        p.nonfinite = bad;
+        for (int q = 0; q < 3; ++q) {
+            p.mn[q] = acc.mn[q];
+            p.mx[q] = acc.mx[q];
+        }
+        p.nonfinite = acc.bad;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         BoundsPartial out = sp[0];
-        for (int w = 1; w < kBlock / 64; ++w)
+        for (int w = 1; w < kWaves; ++w) {
             for (int p = 0; p < 3; ++p) {
                 out.mn[p] = fminf(out.mn[p], sp[w].mn[p]);
                 out.mx[p] = fmaxf(out.mx[p], sp[w].mx[p]);
-                out.nonfinite |= sp[w].nonfinite;
             }
+            out.nonfinite |= sp[w].nonfinite;
+        }
         out.pad = 0;
         part[blockIdx.x] = out;
     }
@@ -175,11 +214,12 @@ __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, 
     float mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     int bad = 0;
     for (int b = lane_id(); b < nparts; b += 64) {
+        const BoundsPartial pb = part[b];
         for (int p = 0; p < 3; ++p) {
-            mn[p] = fminf(mn[p], part[b].mn[p]);
-            mx[p] = fmaxf(mx[p], part[b].mx[p]);
+            mn[p] = fminf(mn[p], pb.mn[p]);
+            mx[p] = fmaxf(mx[p], pb.mx[p]);
         }
-        bad |= part[b].nonfinite;
+        bad |= pb.nonfinite;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -190,10 +230,11 @@ __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, 
         bad |= __shfl_xor(bad, o);
     }
     if (lane_id() != 0) return;
-    // Cell edge r (1 + 2^-10) / cell_div: the margin absorbs the float32 rounding
-    // of the key computation (at most 3 * 2^-24 * G cells per point, G <= 1024),
-    // so two points whose float32 distance test can pass land at most cell_div
-    // cells apart along every binned axis.
+    // Cell edge r (1 + 2^-10) / cell_div.  A pair that passes the float32 test has
+    // |x_p - y_p| < r exactly along every coordinate (partial sums never exceed D,
+    // rounding is monotone); the 2^-10 margin absorbs the float32 rounding of the
+    // key computation (at most 3 * 2^-24 * G cells per point, G <= 1024), so such
+    // a pair lands at most cell_div cells apart along every binned axis.
     const float cbase = (r * 1.0009765625f) / static_cast<float>(cell_div);
     float c[3], ext[3];
     int G[3];
@@ -237,6 +278,8 @@ __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, 
     out->pad = 0;
 }
 
+// Clamping is monotone and moves no coordinate by more than the clamp, so two
+// points that are at most R cells apart stay at most R cells apart.
 __device__ __forceinline__ int cell_coord(float x, float lo, float inv_c, int G) {
     float q = floorf((x - lo) * inv_c);
     q = fmaxf(q, 0.0f);  // also maps NaN to 0
@@ -244,20 +287,26 @@ __device__ __forceinline__ int cell_coord(float x, float lo, float inv_c, int G)
     return static_cast<int>(q);
 }
 
-__global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ X, int n, int d,
+constexpr int kMaxCellTiles = ((1 << 22) + 1 + kScanTile - 1) / kScanTile;
+
+__global__ __launch_bounds__(kKeysBlock) void k_keys(const float *__restrict__ X, int n, int d,
                                                  int d0, int d1, int d2, float r, int cell_div,
                                                  int cells_max,
                                                  const BoundsPartial *__restrict__ part, int nparts,
                                                  Plan *__restrict__ plan_out,
                                                  unsigned int *__restrict__ key,
                                                  unsigned int *__restrict__ rank,
-                                                 unsigned int *__restrict__ cell_count) {
+                                                 unsigned int *__restrict__ cell_count,
+                                                 unsigned long long *__restrict__ sums_cells) {
     __shared__ Plan P;
+    __shared__ unsigned int tile_count[kMaxCellTiles];
     if (wave_id() == 0) derive_plan(part, nparts, r, cell_div, cells_max, &P);
+    const int ntiles = (cells_max + 1 + kScanTile - 1) / kScanTile;
+    for (int t = threadIdx.x; t < ntiles; t += kKeysBlock) tile_count[t] = 0u;
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) *plan_out = P;
     if (P.abort) return;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    for (int i = blockIdx.x * kKeysBlock + threadIdx.x; i < n; i += gridDim.x * kKeysBlock) {
         const float *row = X + static_cast<size_t>(i) * d;
         const int u0 = cell_coord(row[d0], P.lo[0], P.inv_c[0], P.G[0]);
         const int u1 = cell_coord(row[d1], P.lo[1], P.inv_c[1], P.G[1]);
@@ -265,33 +314,23 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float *__restrict__ X, in
         const unsigned int k = static_cast<unsigned int>((u2 * P.G[1] + u1) * P.G[0] + u0);
         key[i] = k;
         rank[i] = atomicAdd(&cell_count[k], 1u);
+        atomicAdd(&tile_count[k / kScanTile], 1u);
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += kKeysBlock)
+        if (tile_count[t]) atomicAdd(&sums_cells[t], static_cast<unsigned long long>(tile_count[t]));
 }
 
 // ------------------------------------------------------------------- scans
 
-__global__ __launch_bounds__(kBlock) void k_tile_sums(const unsigned int *__restrict__ in,
-                                                      int host_len, const int *__restrict__ dev_len,
-                                                      unsigned long long *__restrict__ sums) {
-    __shared__ unsigned long long scratch[kBlock / 64];
-    const long long len = dev_len ? *dev_len : host_len;
-    const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
-    unsigned long long s = 0;
-    for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
-        const long long idx = base + k;
-        if (idx < len) s += in[idx];
-    }
-    s = block_sum(s, scratch);
-    if (threadIdx.x == 0) sums[blockIdx.x] = s;
-}
-
-// out[i] = sum of in[0..i) for i in [0, len]; out[len] is the total.
+// out[i] = sum of in[0..i) for i in [0, len]; out[len] is the total.  sums[t] holds
+// the total of tile t (kScanTile elements).
 template <typename OutT>
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__restrict__ in,
                                                        int host_len, const int *__restrict__ dev_len,
                                                        const unsigned long long *__restrict__ sums,
                                                        OutT *__restrict__ out) {
-    __shared__ unsigned long long scratch[kBlock / 64];
+    __shared__ unsigned long long scratch[kWaves];
     const long long len = dev_len ? *dev_len : host_len;
     const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
     if (base > len) return;
@@ -319,7 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__res
 
 // ----------------------------------------------------------------- scatter
 
-__global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X, int n, int d, int dpad,
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X, int n, int d, int vec4,
                                                     const unsigned int *__restrict__ key,
                                                     const unsigned int *__restrict__ rank,
                                                     const unsigned int *__restrict__ cell_start,
@@ -329,66 +369,80 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X,
     if (plan->abort) return;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const unsigned int slot = cell_start[key[i]] + rank[i];
-        const float *row = X + static_cast<size_t>(i) * d;
-        float *out = sorted + static_cast<size_t>(slot) * dpad;
-        for (int k = 0; k < d; ++k) out[k] = row[k];
-        for (int k = d; k < dpad; ++k) out[k] = 0.0f;
+        float row[DP];
+        if (vec4) {
+            const float4 *src = reinterpret_cast<const float4 *>(X + static_cast<size_t>(i) * d);
+#pragma unroll
+            for (int k = 0; k < DP / 4; ++k) {
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (4 * k < d) v = src[k];
+                row[4 * k] = v.x;
+                row[4 * k + 1] = v.y;
+                row[4 * k + 2] = v.z;
+                row[4 * k + 3] = v.w;
+            }
+        } else {
+            const float *src = X + static_cast<size_t>(i) * d;
+#pragma unroll
+            for (int k = 0; k < DP; ++k) row[k] = k < d ? src[k] : 0.0f;
+        }
+        float4 *out = reinterpret_cast<float4 *>(sorted + static_cast<size_t>(slot) * DP);
+#pragma unroll
+        for (int k = 0; k < DP / 4; ++k)
+            out[k] = make_float4(row[4 * k], row[4 * k + 1], row[4 * k + 2], row[4 * k + 3]);
         sorted_id[slot] = static_cast<unsigned int>(i);
     }
 }
 
 // ------------------------------------------------------------ neighbour runs
 
-// The neighbour cells of `cell` form (2*reach+1)^2 runs that are contiguous in
-// cell order (x is the fastest axis).  Threads of wave 0 build one run each and
-// publish run starts and the prefix of run lengths in LDS.  Returns nothing;
-// run_pre[nruns] is the candidate count.  Must be called by the whole block.
-__device__ void build_runs(unsigned int cell, const Plan &P, const unsigned int *__restrict__ cell_start,
-                           unsigned int *run_start, unsigned int *run_pre, int *nruns_out) {
+// The neighbour cells of `cell` form (2R+1)^2 runs that are contiguous in cell
+// order (x is the fastest axis).  Lane t < (2R+1)^2 builds run t: its first sorted
+// row (start) and the number of candidate rows before it (pre).  Returns the
+// candidate count, the same in every lane.  Call with the whole wave active.
+__device__ __forceinline__ unsigned int wave_runs(unsigned int cell, const Plan &P,
+                                                  const unsigned int *__restrict__ cell_start,
+                                                  unsigned int &start, unsigned int &pre) {
     const int G0 = P.G[0], G1 = P.G[1], G2 = P.G[2];
     const int ux = static_cast<int>(cell % static_cast<unsigned int>(G0));
     const int uy = static_cast<int>((cell / static_cast<unsigned int>(G0)) % static_cast<unsigned int>(G1));
     const int uz = static_cast<int>(cell / static_cast<unsigned int>(G0 * G1));
     const int R = P.reach;
     const int side = 2 * R + 1;
-    const int nr = side * side;
-    if (wave_id() == 0) {
-        const int t = lane_id();
-        unsigned int start = 0, len = 0;
-        if (t < nr) {
-            const int yy = uy + (t % side) - R;
-            const int zz = uz + (t / side) - R;
-            if (yy >= 0 && yy < G1 && zz >= 0 && zz < G2) {
-                const int xlo = max(ux - R, 0), xhi = min(ux + R, G0 - 1);
-                const unsigned int row = static_cast<unsigned int>((zz * G1 + yy) * G0);
-                start = cell_start[row + xlo];
-                len = cell_start[row + xhi + 1] - start;
-            }
-        }
-        const unsigned int inc = wave_inclusive_scan(len);
-        if (t < nr) {
-            run_start[t] = start;
-            run_pre[t + 1] = inc;
-        }
-        if (t == 0) {
-            run_pre[0] = 0;
-            *nruns_out = nr;
+    const int t = lane_id();
+    unsigned int len = 0;
+    start = 0;
+    if (t < side * side) {
+        const int yy = uy + (t % side) - R;
+        const int zz = uz + (t / side) - R;
+        if (yy >= 0 && yy < G1 && zz >= 0 && zz < G2) {
+            const int xlo = max(ux - R, 0), xhi = min(ux + R, G0 - 1);
+            const unsigned int row = static_cast<unsigned int>((zz * G1 + yy) * G0);
+            start = cell_start[row + xlo];
+            len = cell_start[row + xhi + 1] - start;
         }
     }
-    __syncthreads();
+    const unsigned int inc = wave_inclusive_scan(len);
+    pre = inc - len;
+    return uniform(static_cast<unsigned int>(__shfl(inc, 63)));
 }
 
-// Maps candidate number m in [0, run_pre[nruns]) to its sorted row.
-__device__ __forceinline__ unsigned int candidate_row(unsigned int m, const unsigned int *run_start,
-                                                      const unsigned int *run_pre, int nruns) {
+// Maps candidate number m (per lane) to its sorted row: run r is the last run
+// whose `pre` is <= m; empty runs are skipped because the next run has the same
+// pre.  Call with the whole wave active.
+__device__ __forceinline__ unsigned int wave_candidate_row(unsigned int m, int nruns, unsigned int start,
+                                                           unsigned int pre) {
     int r = 0;
-    while (r + 1 < nruns && run_pre[r + 1] <= m) ++r;
-    return run_start[r] + (m - run_pre[r]);
+    for (int t = 1; t < nruns; ++t) {
+        const unsigned int p = uniform(static_cast<unsigned int>(__shfl(pre, t)));
+        r += (m >= p) ? 1 : 0;
+    }
+    const unsigned int s0 = static_cast<unsigned int>(__shfl(start, r));
+    const unsigned int p0 = static_cast<unsigned int>(__shfl(pre, r));
+    return s0 + (m - p0);
 }
 
 // ------------------------------------------------------------------ search
-
-constexpr int kQTile = 64;
 
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sorted,
@@ -398,117 +452,127 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
                                                    unsigned int *__restrict__ kept,
                                                    unsigned long long *__restrict__ tpos,
                                                    unsigned int *__restrict__ temp,
-                                                   unsigned long long temp_cap,
                                                    HeavyEntry *__restrict__ heavy,
-                                                   Counters *__restrict__ ctr) {
-    __shared__ __align__(16) float qx[kQTile * DP];
-    __shared__ unsigned int cnt[kQTile];
-    __shared__ unsigned int lst[kQTile * kListCap];
-    __shared__ unsigned long long qbase[kQTile];
-    __shared__ unsigned int run_start[kMaxRuns];
-    __shared__ unsigned int run_pre[kMaxRuns + 1];
-    __shared__ int nruns_s;
-
+                                                   Counters *__restrict__ ctr,
+                                                   unsigned long long *__restrict__ tested_out) {
+    __shared__ unsigned int lst_all[kWaves][kQTile * kListCap];
+    __shared__ unsigned long long tested_w[kWaves];
     const Plan P = *plan;
     if (P.abort) return;
+    unsigned int *lst = lst_all[wave_id()];
     const int lane = lane_id();
+    const unsigned int n_cells = static_cast<unsigned int>(P.n_cells);
+    const unsigned int total_waves = gridDim.x * kWaves;
+    const int side = 2 * P.reach + 1;
+    const int nruns = side * side;
+    constexpr int kLead = DP < 3 ? DP : 3;  // terms before the first exact rejection test
     unsigned long long tested = 0;
 
-    for (unsigned int cell = blockIdx.x; cell < static_cast<unsigned int>(P.n_cells); cell += gridDim.x) {
-        const unsigned int qs = cell_start[cell], qe = cell_start[cell + 1];
-        if (qs == qe) continue;
-        build_runs(cell, P, cell_start, run_start, run_pre, &nruns_s);
-        const int nruns = nruns_s;
-        const unsigned int M = run_pre[nruns];
-
-        for (unsigned int q0 = qs; q0 < qe; q0 += kQTile) {
-            const int Qn = static_cast<int>(min(static_cast<unsigned int>(kQTile), qe - q0));
-            for (int e = threadIdx.x; e < Qn * DP; e += kBlock) qx[e] = sorted[static_cast<size_t>(q0) * DP + e];
-            for (int q = threadIdx.x; q < kQTile; q += kBlock) cnt[q] = 0u;
-            __syncthreads();
-            tested += static_cast<unsigned long long>(Qn) * M;
-
-            for (unsigned int mb = static_cast<unsigned int>(wave_id()) * 64u; mb < M; mb += kBlock) {
-                const unsigned int m = mb + lane;
-                const bool valid = m < M;
-                unsigned int s = 0;
-                float c[DP];
-                if (valid) {
-                    s = candidate_row(m, run_start, run_pre, nruns);
-                    load_row<DP>(sorted, s, c);
-                } else {
+    // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
+    // workgroups of one XCD take consecutive cells and share their rows in its L2.
+    // Each wave then takes one contiguous, equal share of the cells, so every XCD
+    // gets the same number of cells.
+    const unsigned int nb = gridDim.x;
+    const unsigned int xcd = blockIdx.x % 8u, per = nb / 8u, rest = nb % 8u;
+    const unsigned int lb = xcd < rest ? xcd * (per + 1u) + blockIdx.x / 8u
+                                       : rest * (per + 1u) + (xcd - rest) * per + blockIdx.x / 8u;
+    const unsigned int gw = lb * kWaves + wave_id();
+    const unsigned int cell_lo = static_cast<unsigned int>((static_cast<unsigned long long>(n_cells) * gw) / total_waves);
+    const unsigned int cell_hi =
+        static_cast<unsigned int>((static_cast<unsigned long long>(n_cells) * (gw + 1u)) / total_waves);
+    for (unsigned int cell = cell_lo; cell < cell_hi; ++cell) {
+        const unsigned int qs = uniform(cell_start[cell]);
+        const unsigned int qe = uniform(cell_start[cell + 1]);
+        if (qs != qe) {
+            unsigned int start, pre;
+            const unsigned int M = wave_runs(cell, P, cell_start, start, pre);
+            for (unsigned int q0 = qs; q0 < qe; q0 += kQTile) {
+                const int Qn = static_cast<int>(min(static_cast<unsigned int>(kQTile), qe - q0));
+                unsigned int cnt = 0;  // lane q holds the hit count of query q0 + q
+                // Candidate rows are fetched one chunk ahead so that their latency
+                // overlaps the tests of the current chunk.  Idle lanes read row 0 (any
+                // row is a valid address) and are masked out of every ballot.
+                float cn[DP];
+                unsigned int sn, jn;
+                auto fetch = [&](unsigned int b) {
+                    const unsigned int mm = b + lane;
+                    const unsigned int srow = wave_candidate_row(mm < M ? mm : 0u, nruns, start, pre);
+                    sn = mm < M ? srow : 0u;
+                    load_row<DP>(sorted, sn, cn);
+                    jn = sorted_id[sn];
+                };
+                fetch(0u);
+                for (unsigned int base = 0; base < M; base += 64) {
+                    const bool valid = base + lane < M;
+                    float c[DP];
 #pragma unroll
-                    for (int k = 0; k < DP; ++k) c[k] = 0.0f;
-                }
-                const unsigned int jid = valid ? sorted_id[s] : 0u;
-                for (int q = 0; q < Qn; ++q) {
-                    const float D = sq_dist<DP>(c, &qx[q * DP]);
-                    const bool pass = valid && (D < r2) && (s != q0 + q);
-                    const unsigned long long mask = __ballot(pass);
-                    if (mask) {
-                        const int leader = __ffsll(static_cast<long long>(mask)) - 1;
-                        unsigned int base = 0;
-                        if (lane == leader) base = atomicAdd(&cnt[q], static_cast<unsigned int>(__popcll(mask)));
-                        base = __shfl(base, leader);
+                    for (int k = 0; k < DP; ++k) c[k] = cn[k];
+                    const unsigned int s = sn, jid = jn;
+                    if (base + 64 < M) fetch(base + 64);
+                    const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
+                    for (int q = 0; q < Qn; ++q) {
+                        const unsigned int qslot = q0 + q;
+                        const float *qrow = sorted + static_cast<size_t>(qslot) * DP;
+                        float acc = add_terms<0, kLead, DP>(0.0f, c, qrow);
+                        const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2) & vmask;
+                        if (m1 == 0ull) continue;
+                        acc = add_terms<kLead, DP, DP>(acc, c, qrow);
+                        const unsigned long long m2 = __builtin_amdgcn_ballot_w64(acc < r2) & vmask &
+                                                      ~__builtin_amdgcn_ballot_w64(s == qslot);
+                        if (m2 == 0ull) continue;
+                        const bool pass = (m2 >> lane) & 1ull;
+                        const unsigned int have = __builtin_amdgcn_readlane(cnt, q);
                         if (pass) {
-                            const unsigned int pos = base + prefix_count(mask);
-                            if (pos < kListCap) lst[q * kListCap + pos] = jid;
+                            const unsigned int pos = have + prefix_count(m2);
+                            if (pos < static_cast<unsigned int>(kListCap)) lst[q * kListCap + pos] = jid;
                         }
+                        if (lane == q) cnt += static_cast<unsigned int>(__popcll(m2));
                     }
                 }
-            }
-            __syncthreads();
-
-            // Lists that fit (at most kListCap and at most K entries) go to the edge
-            // store; the others are handed to the long-list kernel.
-            if (wave_id() == 0) {
-                const int q = lane;
-                unsigned int c = 0, take = 0;
-                if (q < Qn) {
-                    c = cnt[q];
-                    take = (c <= static_cast<unsigned int>(kListCap) && c <= static_cast<unsigned int>(K)) ? c : 0u;
-                }
-                const unsigned int inc = wave_inclusive_scan(take);
-                const unsigned int total = __shfl(inc, 63);
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(&ctr->temp_top, static_cast<unsigned long long>(total));
-                base = __shfl(base, 0);
-                if (q < Qn) {
-                    const unsigned int i = sorted_id[q0 + q];
-                    const bool fits = c <= static_cast<unsigned int>(kListCap) && c <= static_cast<unsigned int>(K);
-                    if (fits) {
-                        kept[i] = c;
-                        tpos[i] = base + (inc - take);
-                        qbase[q] = base + (inc - take);
+                tested += static_cast<unsigned long long>(Qn) * M;
+                wave_lds_sync();
+                // Kept counts for every query; short lists are sorted by neighbour id and
+                // stored at a fixed place (kListCap slots per sorted row); longer ones and
+                // capped ones go to the long-list kernel.
+                if (lane < Qn) {
+                    const unsigned int slot = q0 + lane;
+                    const unsigned int i = sorted_id[slot];
+                    kept[i] = min(cnt, static_cast<unsigned int>(K));
+                    if (cnt <= static_cast<unsigned int>(kListCap) && cnt <= static_cast<unsigned int>(K)) {
+                        tpos[i] = static_cast<unsigned long long>(slot) * kListCap;
                     } else {
-                        qbase[q] = ~0ull;
                         const unsigned int h = atomicAdd(&ctr->heavy_count, 1u);
                         HeavyEntry he;
-                        he.slot = q0 + q;
-                        he.count = c;
+                        he.slot = slot;
+                        he.count = cnt;
                         he.cell = cell;
                         he.pad = 0;
                         heavy[h] = he;
-                        if (c > static_cast<unsigned int>(K)) atomicAdd(&ctr->capped, 1u);
+                        if (cnt > static_cast<unsigned int>(K)) atomicAdd(&ctr->capped, 1u);
                     }
                 }
+                // Sort each short list: lane t holds entry t, its rank is the number of
+                // smaller entries, read lane by lane (register reads, no LDS round trips).
+                for (int q = 0; q < Qn; ++q) {
+                    const unsigned int cq = __builtin_amdgcn_readlane(cnt, q);
+                    if (cq == 0u || cq > static_cast<unsigned int>(kListCap) || cq > static_cast<unsigned int>(K))
+                        continue;
+                    const unsigned int j = static_cast<unsigned int>(lane) < cq ? lst[q * kListCap + lane] : 0u;
+                    unsigned int rk = 0;
+                    for (unsigned int u = 0; u < cq; ++u) rk += __builtin_amdgcn_readlane(j, u) < j ? 1u : 0u;
+                    if (static_cast<unsigned int>(lane) < cq) temp[static_cast<size_t>(q0 + q) * kListCap + rk] = j;
+                }
+                wave_lds_sync();
             }
-            __syncthreads();
-            for (int e = threadIdx.x; e < Qn * kListCap; e += kBlock) {
-                const int q = e / kListCap, t = e % kListCap;
-                const unsigned long long b = qbase[q];
-                const unsigned int c = cnt[q];
-                if (b == ~0ull || static_cast<unsigned int>(t) >= c) continue;
-                const unsigned int j = lst[q * kListCap + t];
-                unsigned int rk = 0;
-                for (unsigned int u = 0; u < c; ++u) rk += lst[q * kListCap + u] < j;
-                const unsigned long long pos = b + rk;
-                if (pos < temp_cap) temp[pos] = j;
-            }
-            __syncthreads();
         }
     }
-    if (threadIdx.x == 0 && tested) atomicAdd(&ctr->tested, tested);
+    if (lane == 0) tested_w[wave_id()] = tested;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kWaves; ++w) t += tested_w[w];
+        tested_out[blockIdx.x] = t;
+    }
 }
 
 // --------------------------------------------------------------- long lists
@@ -519,44 +583,63 @@ template <int DP>
 __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sorted,
                                                   const unsigned int *__restrict__ sorted_id,
                                                   const unsigned int *__restrict__ cell_start,
-                                                  const Plan *__restrict__ plan, float r2, int K,
-                                                  unsigned int *__restrict__ kept,
+                                                  const Plan *__restrict__ plan, float r2, int K, int n,
+                                                  const unsigned int *__restrict__ kept,
+                                                  unsigned long long *__restrict__ sums_kept, int tiles_kept,
                                                   unsigned long long *__restrict__ tpos,
                                                   unsigned int *__restrict__ temp,
-                                                  unsigned long long temp_cap,
+                                                  unsigned long long heavy_base, unsigned long long heavy_cap,
                                                   const HeavyEntry *__restrict__ heavy,
                                                   Counters *__restrict__ ctr) {
     __shared__ unsigned int buf[kMaxK];
     __shared__ unsigned int hist[256];
     __shared__ __align__(16) float qv[DP];
-    __shared__ unsigned int run_start[kMaxRuns];
-    __shared__ unsigned int run_pre[kMaxRuns + 1];
-    __shared__ int nruns_s;
-    __shared__ unsigned int h_s, fill_s;
+    __shared__ unsigned int run_start[64];
+    __shared__ unsigned int run_pre[65];
+    __shared__ unsigned int fill_s;
     __shared__ unsigned long long prefix_s, base_s;
     __shared__ unsigned int remaining_s;
+    __shared__ unsigned long long scratch[kWaves];
 
     const Plan P = *plan;
     if (P.abort) return;
-    const unsigned int n_heavy = ctr->heavy_count;
 
-    for (;;) {
-        if (threadIdx.x == 0) h_s = atomicAdd(&ctr->heavy_next, 1u);
-        __syncthreads();
-        const unsigned int h = h_s;
-        if (h >= n_heavy) break;
+    // Totals of kept counts per scan tile (kept is final for every query).
+    for (int t = blockIdx.x; t < tiles_kept; t += gridDim.x) {
+        unsigned long long s = 0;
+        const long long b = static_cast<long long>(t) * kScanTile;
+        for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+            const long long idx = b + k;
+            if (idx < n) s += kept[idx];
+        }
+        s = block_sum(s, scratch);
+        if (threadIdx.x == 0) sums_kept[t] = s;
+    }
+
+    const unsigned int n_heavy = ctr->heavy_count;
+    const int side = 2 * P.reach + 1;
+    const int nruns = side * side;
+    for (unsigned int h = blockIdx.x; h < n_heavy; h += gridDim.x) {
         const HeavyEntry he = heavy[h];
         for (int k = threadIdx.x; k < DP; k += kBlock) qv[k] = sorted[static_cast<size_t>(he.slot) * DP + k];
-        build_runs(he.cell, P, cell_start, run_start, run_pre, &nruns_s);
-        const int nruns = nruns_s;
-        const unsigned int M = run_pre[nruns];
+        if (wave_id() == 0) {
+            unsigned int start, pre;
+            const unsigned int M = wave_runs(he.cell, P, cell_start, start, pre);
+            run_start[lane_id()] = start;
+            run_pre[lane_id()] = pre;
+            if (lane_id() == 0) run_pre[64] = M;
+        }
+        __syncthreads();
+        const unsigned int M = run_pre[64];
         float q[DP];
 #pragma unroll
         for (int k = 0; k < DP; ++k) q[k] = qv[k];
 
         // (D bits << 32 | j) orders hits by (D, j): D is never negative.
         auto hit_key = [&](unsigned int m, bool &ok) -> unsigned long long {
-            const unsigned int s = candidate_row(m, run_start, run_pre, nruns);
+            int r = 0;
+            for (int t = 1; t < nruns; ++t) r += (m >= run_pre[t]) ? 1 : 0;
+            const unsigned int s = run_start[r] + (m - run_pre[r]);
             float c[DP];
             load_row<DP>(sorted, s, c);
             const float D = sq_dist<DP>(c, q);
@@ -632,36 +715,45 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
             }
         }
         if (threadIdx.x == 0) {
-            base_s = atomicAdd(&ctr->temp_top, static_cast<unsigned long long>(n_out));
-            const unsigned int i = sorted_id[he.slot];
-            kept[i] = n_out;
-            tpos[i] = base_s;
+            base_s = atomicAdd(&ctr->heavy_top, static_cast<unsigned long long>(n_out));
+            tpos[sorted_id[he.slot]] = heavy_base + base_s;
         }
         __syncthreads();
         const unsigned long long base = base_s;
-        for (unsigned int t = threadIdx.x; t < n_out; t += kBlock)
-            if (base + t < temp_cap) temp[base + t] = buf[t];
+        if (base + n_out <= heavy_cap)
+            for (unsigned int t = threadIdx.x; t < n_out; t += kBlock) temp[heavy_base + base + t] = buf[t];
         __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------- place
 
-__global__ __launch_bounds__(kBlock) void k_place(int n, const unsigned int *__restrict__ kept,
-                                                  const unsigned long long *__restrict__ tpos,
+// Block b writes the edges of queries [256 b, 256 b + 256): each thread takes
+// output positions in turn and finds its query by binary search over the block's
+// offsets, so stores of src and dst are contiguous across the block.
+__global__ __launch_bounds__(kBlock) void k_place(int n, const unsigned long long *__restrict__ tpos,
                                                   const long long *__restrict__ off,
                                                   const unsigned int *__restrict__ temp,
-                                                  unsigned long long temp_cap,
+                                                  unsigned long long heavy_cap,
                                                   long long *__restrict__ src, long long *__restrict__ dst,
                                                   unsigned long long cap, const Plan *__restrict__ plan,
                                                   const Counters *__restrict__ ctr,
-                                                  Report *__restrict__ report) {
+                                                  const unsigned long long *__restrict__ tested,
+                                                  int search_blocks, Report *__restrict__ report) {
+    __shared__ long long o[kBlock + 1];
+    __shared__ unsigned long long tp[kBlock];
+    __shared__ unsigned long long scratch[kWaves];
     const Plan P = *plan;
     const long long E = P.abort ? 0 : off[n];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0) {
+        unsigned long long t = 0;
+        if (!P.abort)
+            for (int b = threadIdx.x; b < search_blocks; b += kBlock) t += tested[b];
+        t = block_sum(t, scratch);
+        if (threadIdx.x == 0) {
         Report rep;
         rep.n_edges = E;
-        rep.tested = ctr->tested;
+        rep.tested = t;
         rep.abort = P.abort;
         rep.capped = ctr->capped;
         rep.heavy = ctr->heavy_count;
@@ -671,84 +763,113 @@ __global__ __launch_bounds__(kBlock) void k_place(int n, const unsigned int *__r
             rep.c[p] = P.c[p];
         }
         *report = rep;
-    }
-    if (P.abort || static_cast<unsigned long long>(E) > cap || static_cast<unsigned long long>(E) > temp_cap)
-        return;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const unsigned int c = kept[i];
-        const long long o = off[i];
-        const unsigned long long p = tpos[i];
-        for (unsigned int t = 0; t < c; ++t) {
-            src[o + t] = i;
-            dst[o + t] = static_cast<long long>(temp[p + t]);
         }
     }
+    if (P.abort || static_cast<unsigned long long>(E) > cap || ctr->heavy_top > heavy_cap) return;
+    const int i0 = blockIdx.x * kBlock;
+    if (i0 >= n) return;
+    const int cnt = min(kBlock, n - i0);
+    for (int k = threadIdx.x; k <= cnt; k += kBlock) o[k] = off[i0 + k];
+    for (int k = threadIdx.x; k < cnt; k += kBlock) tp[k] = tpos[i0 + k];
+    __syncthreads();
+    const long long first = o[0], last = o[cnt];
+    for (long long p = first + threadIdx.x; p < last; p += kBlock) {
+        int lo = 0, hi = cnt - 1;  // largest q with o[q] <= p
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (o[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        src[p] = i0 + lo;
+        dst[p] = static_cast<long long>(temp[tp[lo] + static_cast<unsigned long long>(p - o[lo])]);
+    }
+}
+
+// Launches the stages whose kernels depend on the padded row width.
+template <int DP>
+void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4, int gk) {
+    auto mark = [&](int stage) {
+        if (a.events) (void)hipEventRecord(a.events[stage], a.stream);
+    };
+    hipLaunchKernelGGL(k_scatter<DP>, dim3(gk), dim3(kBlock), 0, a.stream, a.points, a.n, a.d, vec4, ws.key,
+                       ws.rank, ws.cell_start, ws.plan, ws.sorted, ws.sorted_id);
+    mark(4);
+    hipLaunchKernelGGL(k_search<DP>, dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
+                       ws.cell_start, ws.plan, a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr,
+                       ws.tested);
+    mark(5);
+    const unsigned long long heavy_base = static_cast<unsigned long long>(a.n) * kListCap;
+    hipLaunchKernelGGL(k_heavy<DP>, dim3(kHeavyBlocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
+                       ws.cell_start, ws.plan, a.r2, a.K, a.n, ws.kept, ws.sums_kept, ws.tiles_kept_n, ws.tpos,
+                       ws.temp, heavy_base, a.edge_capacity, ws.heavy, ws.ctr);
 }
 
 template <int DP>
-void launch_search(const LaunchArgs &a, const Workspace &ws, int grid) {
-    hipLaunchKernelGGL(k_search<DP>, dim3(grid), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
-                       ws.cell_start, ws.plan, a.r2, a.K, ws.kept, ws.tpos, ws.temp, a.edge_capacity,
-                       ws.heavy, ws.ctr);
-    if (a.events) hipEventRecord(a.events[5], a.stream);
-    hipLaunchKernelGGL(k_heavy<DP>, dim3(kHeavyBlocks), dim3(kBlock), 0, a.stream, ws.sorted,
-                       ws.sorted_id, ws.cell_start, ws.plan, a.r2, a.K, ws.kept, ws.tpos, ws.temp,
-                       a.edge_capacity, ws.heavy, ws.ctr);
-}
-
-int blocks_for(long long work, int cap) {
-    long long b = (work + kBlock - 1) / kBlock;
-    if (b < 1) b = 1;
-    if (b > cap) b = cap;
-    return static_cast<int>(b);
+int occupancy_blocks() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search<DP>, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    return per_cu * cus;
 }
 
 }  // namespace
 
+int search_blocks_for(int dpad) {
+    switch (dpad) {
+        case 4: return occupancy_blocks<4>();
+        case 8: return occupancy_blocks<8>();
+        case 12: return occupancy_blocks<12>();
+        case 16: return occupancy_blocks<16>();
+        case 24: return occupancy_blocks<24>();
+        case 32: return occupancy_blocks<32>();
+        case 48: return occupancy_blocks<48>();
+        default: return occupancy_blocks<64>();
+    }
+}
+
 hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
     const int cells_max = static_cast<int>(a.cells_max);
     auto mark = [&](int stage) {
-        if (a.events) hipEventRecord(a.events[stage], a.stream);
+        if (a.events) (void)hipEventRecord(a.events[stage], a.stream);
     };
+    const int vec4 = (a.d % 4 == 0 && reinterpret_cast<uintptr_t>(a.points) % 16 == 0) ? 1 : 0;
+    const long long nb = (static_cast<long long>(a.n) + kBlock - 1) / kBlock;
+    const int gk = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
+    const long long nbk = (static_cast<long long>(a.n) + kKeysBlock - 1) / kKeysBlock;
+    const int gkeys = static_cast<int>(nbk < 1 ? 1 : (nbk > 1024 ? 1024 : nbk));
     mark(0);
-    hipLaunchKernelGGL(k_bounds, dim3(kBoundsBlocks), dim3(kBlock), 0, a.stream, a.points, a.n, a.d,
-                       a.dims[0], a.dims[1], a.dims[2], ws.part, ws.cell_count, cells_max, ws.ctr);
+    hipLaunchKernelGGL(k_bounds, dim3(kBoundsBlocks), dim3(kBlock), 0, a.stream, a.points, a.n, a.d, a.dims[0],
+                       a.dims[1], a.dims[2], vec4, ws.part, ws.cell_count, cells_max, ws.sums_cells,
+                       ws.tiles_cells_n, ws.ctr);
     mark(1);
-    const int gk = blocks_for(a.n, 4096);
-    hipLaunchKernelGGL(k_keys, dim3(gk), dim3(kBlock), 0, a.stream, a.points, a.n, a.d, a.dims[0],
-                       a.dims[1], a.dims[2], a.r, a.cell_div, cells_max, ws.part, kBoundsBlocks, ws.plan,
-                       ws.key, ws.rank, ws.cell_count);
+    hipLaunchKernelGGL(k_keys, dim3(gkeys), dim3(kKeysBlock), 0, a.stream, a.points, a.n, a.d, a.dims[0], a.dims[1],
+                       a.dims[2], a.r, a.cell_div, cells_max, ws.part, kBoundsBlocks, ws.plan, ws.key, ws.rank,
+                       ws.cell_count, ws.sums_cells);
     mark(2);
-    const int cell_tiles = static_cast<int>((a.cells_max + 1 + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_tile_sums, dim3(cell_tiles), dim3(kBlock), 0, a.stream, ws.cell_count, 0,
-                       &ws.plan->n_cells, ws.scan_sums);
-    hipLaunchKernelGGL(k_scan_tiles<unsigned int>, dim3(cell_tiles), dim3(kBlock), 0, a.stream,
-                       ws.cell_count, 0, &ws.plan->n_cells, ws.scan_sums, ws.cell_start);
+    hipLaunchKernelGGL(k_scan_tiles<unsigned int>, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream,
+                       ws.cell_count, 0, &ws.plan->n_cells, ws.sums_cells, ws.cell_start);
     mark(3);
-    hipLaunchKernelGGL(k_scatter, dim3(gk), dim3(kBlock), 0, a.stream, a.points, a.n, a.d, a.dpad, ws.key,
-                       ws.rank, ws.cell_start, ws.plan, ws.sorted, ws.sorted_id);
-    mark(4);
-    const int gs = static_cast<int>(a.cells_max < 2048 ? a.cells_max : 2048);
     switch (a.dpad) {
-        case 4: launch_search<4>(a, ws, gs); break;
-        case 8: launch_search<8>(a, ws, gs); break;
-        case 12: launch_search<12>(a, ws, gs); break;
-        case 16: launch_search<16>(a, ws, gs); break;
-        case 24: launch_search<24>(a, ws, gs); break;
-        case 32: launch_search<32>(a, ws, gs); break;
-        case 48: launch_search<48>(a, ws, gs); break;
-        default: launch_search<64>(a, ws, gs); break;
+        case 4: launch_rows<4>(a, ws, vec4, gk); break;
+        case 8: launch_rows<8>(a, ws, vec4, gk); break;
+        case 12: launch_rows<12>(a, ws, vec4, gk); break;
+        case 16: launch_rows<16>(a, ws, vec4, gk); break;
+        case 24: launch_rows<24>(a, ws, vec4, gk); break;
+        case 32: launch_rows<32>(a, ws, vec4, gk); break;
+        case 48: launch_rows<48>(a, ws, vec4, gk); break;
+        default: launch_rows<64>(a, ws, vec4, gk); break;
     }
     mark(6);
-    const int kept_tiles = static_cast<int>((static_cast<long long>(a.n) + 1 + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_tile_sums, dim3(kept_tiles), dim3(kBlock), 0, a.stream, ws.kept, a.n, nullptr,
-                       ws.scan_sums);
-    hipLaunchKernelGGL(k_scan_tiles<long long>, dim3(kept_tiles), dim3(kBlock), 0, a.stream, ws.kept, a.n,
-                       nullptr, ws.scan_sums, ws.off);
+    hipLaunchKernelGGL(k_scan_tiles<long long>, dim3(ws.tiles_kept_n), dim3(kBlock), 0, a.stream, ws.kept, a.n,
+                       nullptr, ws.sums_kept, ws.off);
     mark(7);
-    hipLaunchKernelGGL(k_place, dim3(blocks_for(a.n, 8192)), dim3(kBlock), 0, a.stream, a.n, ws.kept,
-                       ws.tpos, ws.off, ws.temp, a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plan,
-                       ws.ctr, ws.report);
+    hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(nb < 1 ? 1 : nb)), dim3(kBlock), 0, a.stream, a.n,
+                       ws.tpos, ws.off, ws.temp, a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plan, ws.ctr,
+                       ws.tested, a.search_blocks, ws.report);
     mark(8);
     return hipGetLastError();
 }
