@@ -32,6 +32,10 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,6 +44,8 @@ def parse():
     ap.add_argument("--workload", choices=["single", "high", "tiny"], default="single")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cell-div", type=int, default=None)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     return ap.parse_args()
 
 
@@ -68,6 +74,106 @@ def cpu_baseline(spec, X) -> dict:
     return {"value": 1.0 / med, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"one full event (n={spec.n}, d={spec.d}), grid route, single thread, "
                       f"median of 3 runs ({med:.2f} s each)"}
+
+
+def batched_bench(steps: int, warmup: int, log) -> dict:
+    """64 events of 20k-150k hits in one launch sequence, captured in a HIP graph.
+
+    Compares the plain loop (one frnn_build per event) with one batched call and
+    with replays of the captured batch; every batched event's edges are checked
+    byte-for-byte against the same event built alone.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2202_06929_amd import events, frnn, tune
+
+    sizes = events.batched_sizes()
+    evs = [events.generate(events.batched_spec(n, 100 + k))[0] for k, n in enumerate(sizes)]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(np.concatenate(evs)).to(dev)
+    r, K, d = 0.1, 256, 8
+    cfg, treport = tune.tune(pts, offsets, r, K, log=log)
+    log(f"batched: tuned config {cfg} ({treport.get('seconds', 0) * 1e3:.2f} ms per batch)")
+
+    # Plain loop: one call (and one synchronisation) per event.
+    views = [pts[int(offsets[k]):int(offsets[k + 1])] for k in range(len(sizes))]
+    caps = [16 * n for n in sizes]
+    wss = [torch.empty(frnn.workspace_bytes(n, d, c), dtype=torch.uint8, device=dev) for n, c in zip(sizes, caps)]
+    outs = [torch.empty((2, c), dtype=torch.int64, device=dev) for c in caps]
+    alone = []
+    for k in range(len(sizes)):
+        st, E = frnn.build_into(views[k], r, K, wss[k], outs[k][0], outs[k][1], cfg)
+        assert st == frnn.FRNN_OK
+        alone.append(outs[k][:, :E].cpu())
+    def plain_pass():
+        for k in range(len(sizes)):
+            frnn.build_into(views[k], r, K, wss[k], outs[k][0], outs[k][1], cfg)
+    for _ in range(max(1, warmup // 4)):
+        plain_pass()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = max(2, steps // 20)
+    for _ in range(reps):
+        plain_pass()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t) / reps
+
+    # One batched call, then a captured graph of the same batch replayed.
+    total_e = sum(a.shape[1] for a in alone)
+    cap = total_e + 4096
+    ws = torch.empty(frnn.batch_workspace_bytes(offsets, d, cap), dtype=torch.uint8, device=dev)
+    out = torch.empty((2, cap), dtype=torch.int64, device=dev)
+    st, eo = frnn.build_batch_into(pts, offsets, r, K, ws, out[0], out[1], cfg)
+    assert st == frnn.FRNN_OK and eo[-1] == total_e
+    for k in range(len(sizes)):
+        got = out[:, int(eo[k]):int(eo[k + 1])].cpu()
+        assert torch.equal(got, alone[k]), f"event {k}: batched edges differ from the event alone"
+    t = time.perf_counter()
+    for _ in range(reps):
+        frnn.build_batch_into(pts, offsets, r, K, ws, out[0], out[1], cfg)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t) / reps
+
+    eo_dev = torch.zeros(len(sizes) + 2, dtype=torch.int64, device=dev)
+    rcfg = frnn.Config(dims=cfg.dims, cell_div=cfg.cell_div, events_resident=True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        st = frnn.build_batch_async(pts, offsets, r, K, ws, out[0], out[1], eo_dev, rcfg)
+        assert st == frnn.FRNN_OK
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        st = frnn.build_batch_async(pts, offsets, r, K, ws, out[0], out[1], eo_dev, rcfg)
+    assert st == frnn.FRNN_OK
+    for _ in range(3):
+        out.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        e_host = eo_dev.cpu().numpy()
+        assert e_host[-1] == 0 and np.array_equal(e_host[:-1], eo), "graph replay: wrong edge ranges"
+        for k in (0, len(sizes) // 2, len(sizes) - 1):
+            assert torch.equal(out[:, int(eo[k]):int(eo[k + 1])].cpu(), alone[k]), "graph replay: edges differ"
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        graph.replay()
+    end.record()
+    torch.cuda.synchronize()
+    t_graph = start.elapsed_time(end) * 1e-3 / reps
+    n_ev = len(sizes)
+    return {"workload": f"batched: {n_ev} events, hits uniform in [20000, 150000] (total {int(offsets[-1])}), "
+                        "8-D float32, r=0.1, K=256",
+            "config": {"dims": list(cfg.dims) if cfg.dims else None, "cell_div": cfg.cell_div},
+            "events_per_s_plain_loop": n_ev / t_plain, "events_per_s_batched_call": n_ev / t_batch,
+            "events_per_s_graph": n_ev / t_graph, "ms_per_batch_graph": t_graph * 1e3,
+            "edges_per_s_graph": total_e / t_graph, "edges": total_e,
+            "speedup_graph_vs_plain": t_plain / t_graph, "parity": "every event identical to the event alone",
+            "tune": treport.get("all")}
 
 
 def main():
@@ -149,6 +255,8 @@ def main():
         "candidates": st["candidates"],
         "roofline": roofline, "roofline_hbm": roofline_hbm,
     }
+    if not args.no_batched:
+        result["batched"] = batched_bench(args.steps, args.warmup, log)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec, X)
     print(json.dumps(result), flush=True)

@@ -70,6 +70,11 @@ typedef struct frnn_config {
 /* frnn_config.flags: time every stage with HIP events on the call's stream and
  * report the durations in frnn_stats.stage_ms (adds a few microseconds). */
 #define FRNN_FLAG_TIMING 1
+/* frnn_config.flags, frnn_build_batch_async only: the workspace already holds the
+ * event table of an earlier call with the same event_offsets and d, so nothing is
+ * copied to the device and the call only enqueues kernels (it can then be
+ * captured into a HIP graph and replayed). */
+#define FRNN_FLAG_EVENTS_RESIDENT 2
 
 /* Stages reported in frnn_stats.stage_ms. */
 enum frnn_stage {
@@ -120,6 +125,47 @@ int frnn_build(const float *points, int64_t n, int32_t d, float r, int32_t K,
                void *workspace, size_t workspace_bytes,
                int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *n_edges,
                const frnn_config *config, frnn_stats *stats, void *stream);
+
+/* Bytes of device workspace frnn_build_batch needs for the given events (see
+ * below) and room for edge_capacity edges in total.  Returns 0 for invalid
+ * arguments. */
+size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events, int32_t d,
+                                  int64_t edge_capacity);
+
+/* Builds the FRNN graphs of several independent events in one pass (one launch
+ * sequence and one synchronisation for the whole batch).  Each event is searched
+ * on its own: its own grid, no edges between events.
+ *   points          device, float32, the events' rows back to back; event e is rows
+ *                   [event_offsets[e], event_offsets[e+1]) of points (row-major, d columns)
+ *   event_offsets   host, int64 [n_events + 1], non-decreasing; 1 <= n_events <= 65536;
+ *                   total rows < 2^31
+ *   src, dst        device, int64 [edge_capacity] each: the events' edge lists back to back;
+ *                   indices are local to their event (0 .. n_e - 1); each list sorted by (i, j)
+ *   edge_offsets    host, int64 [n_events + 1]: event e's edges are
+ *                   [edge_offsets[e], edge_offsets[e+1]); on FRNN_ERR_CAPACITY only
+ *                   edge_offsets[n_events] is set, to the total needed
+ * Other arguments as for frnn_build; a non-finite coordinate in any event fails the
+ * whole batch with FRNN_ERR_NONFINITE.  stats describe the batch (grid fields: event 0). */
+int frnn_build_batch(const float *points, const int64_t *event_offsets, int32_t n_events, int32_t d,
+                     float r, int32_t K, void *workspace, size_t workspace_bytes,
+                     int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *edge_offsets,
+                     const frnn_config *config, frnn_stats *stats, void *stream);
+
+/* frnn_build_batch without waiting: checks the arguments, enqueues the work on
+ * `stream` and returns.  Results stay on the device:
+ *   edge_offsets_device  device, int64 [n_events + 2]: entries 0..n_events as for
+ *                        frnn_build_batch's edge_offsets (entry n_events is the total E,
+ *                        also when it exceeds edge_capacity), then a status word:
+ *                        0 ok, FRNN_ERR_NONFINITE or FRNN_ERR_CAPACITY.
+ * The total row count must be positive.  FRNN_FLAG_TIMING is not accepted.  With
+ * FRNN_FLAG_EVENTS_RESIDENT (see above) only kernels are enqueued, so the call can
+ * be captured into a HIP graph; the points, workspace and outputs must then stay
+ * at the same addresses for every replay.  Calls that share a workspace must not
+ * overlap in time. */
+int frnn_build_batch_async(const float *points, const int64_t *event_offsets, int32_t n_events, int32_t d,
+                           float r, int32_t K, void *workspace, size_t workspace_bytes,
+                           int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *edge_offsets_device,
+                           const frnn_config *config, void *stream);
 
 /* Static name of a status code. */
 const char *frnn_status_string(int status);

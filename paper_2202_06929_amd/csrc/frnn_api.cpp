@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "frnn.h"
 #include "frnn_internal.h"
@@ -16,7 +17,8 @@
 namespace frnn {
 
 int64_t cells_max_for(int64_t n) {
-    int64_t c = 4 * n;
+    if (n <= 0) return 1;
+    int64_t c = 2 * n;
     if (c < (int64_t{1} << 15)) c = int64_t{1} << 15;
     if (c > (int64_t{1} << 22)) c = int64_t{1} << 22;
     return c;
@@ -53,7 +55,7 @@ bool config_ok(const frnn_config *c, int d) {
     }
     if (c->cell_div < 0 || c->cell_div > kMaxReach) return false;
     if (c->tile != 0 && c->tile != 32 && c->tile != 64) return false;
-    if (c->flags & ~FRNN_FLAG_TIMING) return false;
+    if (c->flags & ~(FRNN_FLAG_TIMING | FRNN_FLAG_EVENTS_RESIDENT)) return false;
     return true;
 }
 
@@ -79,31 +81,53 @@ thread_local bool t_events_ready = false;
 
 }  // namespace
 
-Workspace layout(void *base, int64_t n, int d, int64_t edge_capacity) {
+long long describe_events(const int64_t *event_offsets, int n_events, EventDesc *descs) {
+    long long cells = 0;
+    for (int e = 0; e < n_events; ++e) {
+        const int64_t n = event_offsets[e + 1] - event_offsets[e];
+        const int64_t cm = cells_max_for(n);
+        if (descs) {
+            descs[e].row0 = event_offsets[e] - event_offsets[0];
+            descs[e].cell0 = cells;
+            descs[e].n = static_cast<int>(n);
+            descs[e].cells_max = static_cast<int>(cm);
+            descs[e].tile0 = static_cast<int>(cells / kScanTile);
+            descs[e].pad = 0;
+        }
+        cells += cm;
+    }
+    return cells;
+}
+
+Workspace layout(void *base, long long rows, long long cells, int n_events, int d, int64_t edge_capacity) {
     const int dpad = dpad_for(d);
-    const int64_t cells = cells_max_for(n);
     const int64_t tiles_cells = (cells + 1 + kScanTile - 1) / kScanTile;
-    const int64_t tiles_kept = (n + 1 + kScanTile - 1) / kScanTile;
+    const int64_t tiles_kept = (rows + 1 + kScanTile - 1) / kScanTile;
     Carver cv{static_cast<char *>(base)};
     Workspace ws;
-    ws.part = cv.take<BoundsPartial>(kBoundsBlocks);
-    ws.plan = cv.take<Plan>(1);
+    ws.ev = cv.take<EventDesc>(n_events);
+    ws.plans = cv.take<Plan>(n_events);
+    ws.part = cv.take<BoundsPartial>(static_cast<size_t>(n_events) * kBoundsBlocks);
     ws.ctr = cv.take<Counters>(1);
     ws.report = cv.take<Report>(1);
-    ws.key = cv.take<unsigned int>(n);
-    ws.rank = cv.take<unsigned int>(n);
+    ws.edge_off = cv.take<long long>(static_cast<size_t>(n_events) + 2);
+    ws.key = cv.take<unsigned int>(rows);
+    ws.rank = cv.take<unsigned int>(rows);
     ws.cell_count = cv.take<unsigned int>(cells);
     ws.cell_start = cv.take<unsigned int>(cells + 1);
     ws.sums_cells = cv.take<unsigned long long>(tiles_cells);
     ws.sums_kept = cv.take<unsigned long long>(tiles_kept);
-    ws.sorted = cv.take<float>(static_cast<size_t>(n) * dpad);
-    ws.sorted_id = cv.take<unsigned int>(n);
-    ws.kept = cv.take<unsigned int>(n);
-    ws.tpos = cv.take<unsigned long long>(n);
-    ws.off = cv.take<long long>(n + 1);
-    ws.heavy = cv.take<HeavyEntry>(n);
-    ws.temp = cv.take<unsigned int>(static_cast<size_t>(n) * kListCap + static_cast<size_t>(edge_capacity));
+    ws.sorted = cv.take<float>(static_cast<size_t>(rows) * dpad);
+    ws.sorted_id = cv.take<unsigned int>(rows);
+    ws.sorted_key = cv.take<unsigned int>(rows);
+    ws.kept = cv.take<unsigned int>(rows);
+    ws.tpos = cv.take<unsigned long long>(rows);
+    ws.off = cv.take<long long>(rows + 1);
+    ws.heavy = cv.take<HeavyEntry>(rows);
+    ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap + static_cast<size_t>(edge_capacity));
     ws.tested = cv.take<unsigned long long>(kMaxSearchBlocks);
+    ws.rows = rows;
+    ws.cells = cells;
     ws.tiles_cells_n = static_cast<int>(tiles_cells);
     ws.tiles_kept_n = static_cast<int>(tiles_kept);
     ws.total_bytes = cv.at;
@@ -114,9 +138,147 @@ Workspace layout(void *base, int64_t n, int d, int64_t edge_capacity) {
 
 using namespace frnn;
 
+namespace {
+
+// Arguments shared by the single-event and batched calls.
+int check_common(int32_t d, float r, int32_t K, int64_t edge_capacity, const frnn_config *config) {
+    if (d < 3 || d > FRNN_MAX_D || !(r > 0.0f) || !isfinite(r) || K < 1 || K > FRNN_MAX_K || edge_capacity < 0 ||
+        !config_ok(config, d))
+        return FRNN_ERR_ARG;
+    return FRNN_OK;
+}
+
+int check_events(const int64_t *event_offsets, int32_t n_events, long long *rows, int *max_n, long long *cells) {
+    if (!event_offsets || n_events < 1 || n_events > kMaxEvents) return FRNN_ERR_ARG;
+    long long mx = 0;
+    for (int e = 0; e < n_events; ++e) {
+        const int64_t n = event_offsets[e + 1] - event_offsets[e];
+        if (n < 0) return FRNN_ERR_ARG;
+        if (n > mx) mx = n;
+    }
+    *rows = event_offsets[n_events] - event_offsets[0];
+    if (*rows >= (int64_t{1} << 31)) return FRNN_ERR_UNSUPPORTED;
+    *cells = describe_events(event_offsets, n_events, nullptr);
+    if (*cells >= (int64_t{1} << 31)) return FRNN_ERR_UNSUPPORTED;
+    *max_n = static_cast<int>(mx);
+    return FRNN_OK;
+}
+
+// Enqueues the pipeline for checked arguments (descriptors uploaded first unless
+// they are already resident).  Returns a status and the workspace view.
+int enqueue(const float *points, const EventDesc *descs, int n_events, long long rows, long long cells, int max_n,
+            int32_t d, float r, int32_t K, void *workspace, int64_t *src, int64_t *dst, int64_t edge_capacity,
+            const frnn_config *config, hipStream_t stream, bool upload, long long *edge_off_out, Workspace *ws_out,
+            bool *timing_out) {
+    int dims[3] = {d - 3, d - 2, d - 1};
+    if (config && config->dims[0] != config->dims[1])
+        for (int p = 0; p < 3; ++p) dims[p] = config->dims[p];
+    LaunchArgs a;
+    a.points = points;
+    a.n_events = n_events;
+    a.max_n = max_n;
+    a.d = d;
+    a.dpad = dpad_for(d);
+    for (int p = 0; p < 3; ++p) a.dims[p] = dims[p];
+    a.r = r;
+    a.r2 = r * r;
+    a.K = K;
+    a.cell_div = (config && config->cell_div) ? config->cell_div : 1;
+    a.edge_capacity = static_cast<unsigned long long>(edge_capacity);
+    a.src = reinterpret_cast<long long *>(src);
+    a.dst = reinterpret_cast<long long *>(dst);
+    a.stream = stream;
+    a.search_blocks = search_blocks_cached(a.dpad);
+    a.ev0 = descs ? descs[0] : EventDesc{};
+    a.ev_from_arg = n_events == 1 ? 1 : 0;
+    a.edge_off_out = edge_off_out;
+    const Workspace ws = layout(workspace, rows, cells, n_events, d, edge_capacity);
+    const bool timing = config && (config->flags & FRNN_FLAG_TIMING);
+    a.events = nullptr;
+    if (timing) {
+        if (!t_events_ready) {
+            for (auto &e : t_events)
+                if (hipEventCreate(&e) != hipSuccess) return FRNN_ERR_HIP;
+            t_events_ready = true;
+        }
+        a.events = t_events;
+    }
+    // Batches: descriptors go to the device first (a pageable copy; the source is
+    // consumed before the call returns).
+    if (n_events > 1 && upload &&
+        hipMemcpyAsync(ws.ev, descs, sizeof(EventDesc) * n_events, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return FRNN_ERR_HIP;
+    if (enqueue_build(a, ws) != hipSuccess) return FRNN_ERR_HIP;
+    *ws_out = ws;
+    *timing_out = timing;
+    return FRNN_OK;
+}
+
+// Enqueues, copies the report (and the per-event edge ranges) back and waits.
+int run(const float *points, const EventDesc *descs, int n_events, long long rows, long long cells, int max_n,
+        int32_t d, float r, int32_t K, void *workspace, int64_t *src, int64_t *dst, int64_t edge_capacity,
+        const frnn_config *config, frnn_stats *stats, hipStream_t stream, Report *rep_out,
+        int64_t *edge_offsets_host) {
+    if (!t_report) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, sizeof(Report), hipHostMallocDefault) != hipSuccess) return FRNN_ERR_HIP;
+        t_report = static_cast<Report *>(p);
+    }
+    Workspace ws;
+    bool timing = false;
+    const int st = enqueue(points, descs, n_events, rows, cells, max_n, d, r, K, workspace, src, dst, edge_capacity,
+                           config, stream, true, nullptr, &ws, &timing);
+    if (st != FRNN_OK) return st;
+    if (hipMemcpyAsync(t_report, ws.report, sizeof(Report), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return FRNN_ERR_HIP;
+    if (edge_offsets_host &&
+        hipMemcpyAsync(edge_offsets_host, ws.edge_off, sizeof(long long) * (n_events + 1), hipMemcpyDeviceToHost,
+                       stream) != hipSuccess)
+        return FRNN_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return FRNN_ERR_HIP;
+    *rep_out = *t_report;
+    if (stats) {
+        stats->n_edges = rep_out->n_edges;
+        stats->candidates = static_cast<int64_t>(rep_out->tested);
+        stats->n_cells = rep_out->n_cells;
+        for (int p = 0; p < 3; ++p) {
+            stats->grid[p] = rep_out->G[p];
+            stats->cell[p] = rep_out->c[p];
+        }
+        stats->capped_queries = static_cast<int32_t>(rep_out->capped);
+        stats->overflow_queries = static_cast<int32_t>(rep_out->heavy);
+        if (timing)
+            for (int k = 0; k < FRNN_STAGES; ++k)
+                if (hipEventElapsedTime(&stats->stage_ms[k], t_events[k], t_events[k + 1]) != hipSuccess)
+                    return FRNN_ERR_HIP;
+    }
+    if (rep_out->abort) return FRNN_ERR_NONFINITE;
+    if (rep_out->n_edges > edge_capacity) return FRNN_ERR_CAPACITY;
+    return FRNN_OK;
+}
+
+void init_stats(frnn_stats *stats, const frnn_config *config, int d) {
+    if (!stats) return;
+    memset(stats, 0, sizeof(*stats));
+    const bool set = config && config->dims[0] != config->dims[1];
+    for (int p = 0; p < 3; ++p) stats->dims[p] = set ? config->dims[p] : d - 3 + p;
+}
+
+}  // namespace
+
 extern "C" size_t frnn_workspace_bytes(int64_t n, int32_t d, int64_t edge_capacity) {
     if (n < 0 || n >= (int64_t{1} << 31) || d < 3 || d > FRNN_MAX_D || edge_capacity < 0) return 0;
-    return layout(nullptr, n, d, edge_capacity).total_bytes;
+    const int64_t offs[2] = {0, n};
+    return layout(nullptr, n, describe_events(offs, 1, nullptr), 1, d, edge_capacity).total_bytes;
+}
+
+extern "C" size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events, int32_t d,
+                                             int64_t edge_capacity) {
+    long long rows = 0, cells = 0;
+    int max_n = 0;
+    if (d < 3 || d > FRNN_MAX_D || edge_capacity < 0) return 0;
+    if (check_events(event_offsets, n_events, &rows, &max_n, &cells) != FRNN_OK) return 0;
+    return layout(nullptr, rows, cells, n_events, d, edge_capacity).total_bytes;
 }
 
 extern "C" const char *frnn_status_string(int status) {
@@ -136,81 +298,81 @@ extern "C" int frnn_build(const float *points, int64_t n, int32_t d, float r, in
                           void *workspace, size_t workspace_bytes, int64_t *src, int64_t *dst,
                           int64_t edge_capacity, int64_t *n_edges, const frnn_config *config,
                           frnn_stats *stats, void *stream) {
-    if (!n_edges || n < 0 || d < 3 || d > FRNN_MAX_D || !(r > 0.0f) || !isfinite(r) || K < 1 ||
-        K > FRNN_MAX_K || edge_capacity < 0 || !config_ok(config, d))
-        return FRNN_ERR_ARG;
+    if (!n_edges || n < 0) return FRNN_ERR_ARG;
+    const int st = check_common(d, r, K, edge_capacity, config);
+    if (st != FRNN_OK) return st;
     if (n >= (int64_t{1} << 31)) return FRNN_ERR_UNSUPPORTED;
-    int dims[3] = {d - 3, d - 2, d - 1};
-    if (config && config->dims[0] != config->dims[1])
-        for (int p = 0; p < 3; ++p) dims[p] = config->dims[p];
-    const int cell_div = (config && config->cell_div) ? config->cell_div : 1;
-    if (stats) {
-        memset(stats, 0, sizeof(*stats));
-        for (int p = 0; p < 3; ++p) stats->dims[p] = dims[p];
-    }
+    init_stats(stats, config, d);
     *n_edges = 0;
     if (n == 0) return FRNN_OK;
     if (!points || !workspace || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
-    const size_t need = frnn_workspace_bytes(n, d, edge_capacity);
-    if (workspace_bytes < need) return FRNN_ERR_WORKSPACE;
+    if (workspace_bytes < frnn_workspace_bytes(n, d, edge_capacity)) return FRNN_ERR_WORKSPACE;
+    const int64_t offs[2] = {0, n};
+    EventDesc desc;
+    const long long cells = describe_events(offs, 1, &desc);
+    Report rep;
+    const int rs = run(points, &desc, 1, n, cells, static_cast<int>(n), d, r, K, workspace, src, dst, edge_capacity,
+                       config, stats, static_cast<hipStream_t>(stream), &rep, nullptr);
+    if (rs == FRNN_OK || rs == FRNN_ERR_CAPACITY) *n_edges = rep.n_edges;
+    return rs;
+}
 
-    LaunchArgs a;
-    a.points = points;
-    a.n = static_cast<int>(n);
-    a.d = d;
-    a.dpad = dpad_for(d);
-    for (int p = 0; p < 3; ++p) a.dims[p] = dims[p];
-    a.r = r;
-    a.r2 = r * r;
-    a.K = K;
-    a.cell_div = cell_div;
-    a.tile = (config && config->tile) ? config->tile : 64;
-    a.cells_max = cells_max_for(n);
-    a.edge_capacity = static_cast<unsigned long long>(edge_capacity);
-    a.src = reinterpret_cast<long long *>(src);
-    a.dst = reinterpret_cast<long long *>(dst);
-    a.stream = static_cast<hipStream_t>(stream);
-    a.search_blocks = search_blocks_cached(a.dpad);
-    const Workspace ws = layout(workspace, n, d, edge_capacity);
-    const bool timing = config && (config->flags & FRNN_FLAG_TIMING);
-    a.events = nullptr;
-    if (timing) {
-        if (!t_events_ready) {
-            for (auto &e : t_events)
-                if (hipEventCreate(&e) != hipSuccess) return FRNN_ERR_HIP;
-            t_events_ready = true;
-        }
-        a.events = t_events;
+extern "C" int frnn_build_batch(const float *points, const int64_t *event_offsets, int32_t n_events, int32_t d,
+                                float r, int32_t K, void *workspace, size_t workspace_bytes, int64_t *src,
+                                int64_t *dst, int64_t edge_capacity, int64_t *edge_offsets,
+                                const frnn_config *config, frnn_stats *stats, void *stream) {
+    if (!edge_offsets) return FRNN_ERR_ARG;
+    const int st = check_common(d, r, K, edge_capacity, config);
+    if (st != FRNN_OK) return st;
+    long long rows = 0, cells = 0;
+    int max_n = 0;
+    const int se = check_events(event_offsets, n_events, &rows, &max_n, &cells);
+    if (se != FRNN_OK) return se;
+    init_stats(stats, config, d);
+    for (int e = 0; e <= n_events; ++e) edge_offsets[e] = 0;
+    if (rows == 0) return FRNN_OK;
+    if (!points || !workspace || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
+    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d, edge_capacity).total_bytes)
+        return FRNN_ERR_WORKSPACE;
+    std::vector<EventDesc> descs(n_events);
+    describe_events(event_offsets, n_events, descs.data());
+    Report rep;
+    const float *first = points + static_cast<size_t>(event_offsets[0]) * d;
+    const int rs = run(first, descs.data(), n_events, rows, cells, max_n, d, r, K, workspace, src, dst,
+                       edge_capacity, config, stats, static_cast<hipStream_t>(stream), &rep, edge_offsets);
+    if (rs == FRNN_ERR_CAPACITY) {
+        for (int e = 0; e < n_events; ++e) edge_offsets[e] = 0;
+        edge_offsets[n_events] = rep.n_edges;
     }
+    return rs;
+}
 
-    if (!t_report) {
-        void *p = nullptr;
-        if (hipHostMalloc(&p, sizeof(Report), hipHostMallocDefault) != hipSuccess) return FRNN_ERR_HIP;
-        t_report = static_cast<Report *>(p);
-    }
-    if (enqueue_build(a, ws) != hipSuccess) return FRNN_ERR_HIP;
-    if (hipMemcpyAsync(t_report, ws.report, sizeof(Report), hipMemcpyDeviceToHost, a.stream) != hipSuccess)
-        return FRNN_ERR_HIP;
-    if (hipStreamSynchronize(a.stream) != hipSuccess) return FRNN_ERR_HIP;
-    const Report rep = *t_report;
-    if (stats) {
-        stats->n_edges = rep.n_edges;
-        stats->candidates = static_cast<int64_t>(rep.tested);
-        stats->n_cells = rep.n_cells;
-        for (int p = 0; p < 3; ++p) {
-            stats->grid[p] = rep.G[p];
-            stats->cell[p] = rep.c[p];
-        }
-        stats->capped_queries = static_cast<int32_t>(rep.capped);
-        stats->overflow_queries = static_cast<int32_t>(rep.heavy);
-        if (timing)
-            for (int k = 0; k < FRNN_STAGES; ++k)
-                if (hipEventElapsedTime(&stats->stage_ms[k], t_events[k], t_events[k + 1]) != hipSuccess)
-                    return FRNN_ERR_HIP;
-    }
-    if (rep.abort) return FRNN_ERR_NONFINITE;
-    *n_edges = rep.n_edges;
-    if (rep.n_edges > edge_capacity) return FRNN_ERR_CAPACITY;
-    return FRNN_OK;
+extern "C" int frnn_build_batch_async(const float *points, const int64_t *event_offsets, int32_t n_events,
+                                      int32_t d, float r, int32_t K, void *workspace, size_t workspace_bytes,
+                                      int64_t *src, int64_t *dst, int64_t edge_capacity,
+                                      int64_t *edge_offsets_device, const frnn_config *config, void *stream) {
+    if (!edge_offsets_device) return FRNN_ERR_ARG;
+    if (config && (config->flags & FRNN_FLAG_TIMING)) return FRNN_ERR_ARG;
+    const int st = check_common(d, r, K, edge_capacity, config);
+    if (st != FRNN_OK) return st;
+    long long rows = 0, cells = 0;
+    int max_n = 0;
+    const int se = check_events(event_offsets, n_events, &rows, &max_n, &cells);
+    if (se != FRNN_OK) return se;
+    if (rows == 0) return FRNN_ERR_ARG;
+    if (!points || !workspace || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
+    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d, edge_capacity).total_bytes)
+        return FRNN_ERR_WORKSPACE;
+    std::vector<EventDesc> descs(n_events);
+    describe_events(event_offsets, n_events, descs.data());
+    const bool resident = config && (config->flags & FRNN_FLAG_EVENTS_RESIDENT);
+    Workspace ws;
+    bool timing = false;
+    const float *first = points + static_cast<size_t>(event_offsets[0]) * d;
+    return enqueue(first, descs.data(), n_events, rows, cells, max_n, d, r, K, workspace, src, dst, edge_capacity,
+                   config, static_cast<hipStream_t>(stream), !resident,
+                   reinterpret_cast<long long *>(edge_offsets_device), &ws, &timing);
 }

@@ -10,7 +10,7 @@ namespace frnn {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kBoundsBlocks = 128;   // partial results of the bounds pass
+constexpr int kBoundsBlocks = 64;    // bounds partials per event
 constexpr int kScanTile = 4096;      // elements per workgroup in the scans
 constexpr int kListCap = 32;         // neighbours a query may collect in the main search
 constexpr int kQTile = 32;           // queries of one cell handled together by a wave
@@ -20,6 +20,20 @@ constexpr int kGridAxisMax = 1024;   // cells per binned axis (bounds the key ro
 constexpr int kMaxK = 4096;
 constexpr int kMaxSearchBlocks = 8192;
 constexpr int kKeysBlock = 1024;     // threads per workgroup of the key/histogram pass
+constexpr int kPlaceBlock = 1024;    // threads per workgroup of the placement pass
+constexpr int kPlaceQueries = 256;   // queries per workgroup of the placement pass
+constexpr int kMaxEvents = 1 << 16;
+
+// One event of a call: its rows in the concatenated points and its share of the
+// cell-key space.  The first event starts at row 0 and cell 0.
+struct EventDesc {
+    long long row0;    // first row of the event
+    long long cell0;   // first cell key of the event
+    int n;             // rows of the event
+    int cells_max;     // cells reserved for the event
+    int tile0;         // first scan tile of the event's cells (cell0 / kScanTile)
+    int pad;
+};
 
 // Per-block min/max of the binned coordinates and a non-finite flag.
 struct BoundsPartial {
@@ -29,7 +43,7 @@ struct BoundsPartial {
     int pad;
 };
 
-// The grid of one call, derived on the device from the bounds.
+// The grid of one event, derived on the device from its bounds.
 struct Plan {
     float lo[3];      // smallest binned coordinate per axis
     float inv_c[3];   // 1 / cell edge per axis (float32)
@@ -41,16 +55,17 @@ struct Plan {
     int pad;
 };
 
-// Counters cleared at the start of every call.
 // Single-address atomics serialise across the chip (about 11 ns each), so these
-// are touched only by rare events (long lists, capped queries).
+// are touched only by rare events (long lists, capped queries, bad input).
 struct Counters {
     unsigned long long heavy_top;  // next free slot of the long-list store
     unsigned int heavy_count;      // queries sent to the long-list path
     unsigned int capped;           // queries with more than K neighbours
+    unsigned int abort;            // some event had a non-finite coordinate
+    unsigned int pad;
 };
 
-// Result summary copied to the host at the end of a call.
+// Result summary copied to the host at the end of a call (event 0's grid).
 struct Report {
     long long n_edges;
     unsigned long long tested;
@@ -66,30 +81,35 @@ struct Report {
 struct HeavyEntry {
     unsigned int slot;    // position of the query in cell order
     unsigned int count;   // |N(i)| before the cap
-    unsigned int cell;    // its cell key
-    unsigned int pad;
+    unsigned int cell;    // its (global) cell key
+    unsigned int event;   // its event
 };
 
 // Device buffers of one call, carved from the caller's workspace.
 struct Workspace {
-    BoundsPartial *part;
-    Plan *plan;
+    EventDesc *ev;              // [n_events]
+    Plan *plans;                // [n_events]
+    BoundsPartial *part;        // [n_events * kBoundsBlocks]
     Counters *ctr;
     Report *report;
-    unsigned int *key;          // [n] cell key of each point
-    unsigned int *rank;         // [n] arrival rank inside its cell
-    unsigned int *cell_count;   // [cells_max] histogram
-    unsigned int *cell_start;   // [cells_max + 1] exclusive scan of the histogram
-    unsigned long long *sums_cells;  // [tiles of cells_max + 1] per-tile histogram totals
-    unsigned long long *sums_kept;   // [tiles of n + 1] per-tile kept totals
-    float *sorted;              // [n, dpad] points in cell order, zero-padded rows
-    unsigned int *sorted_id;    // [n] original index of each sorted row
-    unsigned int *kept;         // [n] neighbours kept per original index
-    unsigned long long *tpos;   // [n] where each query's list sits in `temp`
-    long long *off;             // [n + 1] exclusive scan of kept (output offsets)
-    HeavyEntry *heavy;          // [n]
-    unsigned int *temp;         // [n * kListCap + edge_capacity] neighbour lists
+    long long *edge_off;        // [n_events + 2] first edge of each event, then E, then a status
+    unsigned int *key;          // [rows] cell key of each point
+    unsigned int *rank;         // [rows] arrival rank inside its cell
+    unsigned int *cell_count;   // [cells] histogram
+    unsigned int *cell_start;   // [cells + 1] exclusive scan of the histogram
+    unsigned long long *sums_cells;  // [tiles of cells + 1] per-tile histogram totals
+    unsigned long long *sums_kept;   // [tiles of rows + 1] per-tile kept totals
+    float *sorted;              // [rows, dpad] points in cell order, zero-padded rows
+    unsigned int *sorted_id;    // [rows] original row of each sorted row
+    unsigned int *sorted_key;   // [rows] cell key of each sorted row
+    unsigned int *kept;         // [rows] neighbours kept per original row
+    unsigned long long *tpos;   // [rows] where each query's list sits in `temp`
+    long long *off;             // [rows + 1] exclusive scan of kept (output offsets)
+    HeavyEntry *heavy;          // [rows]
+    unsigned int *temp;         // [rows * kListCap + edge_capacity] neighbour lists
     unsigned long long *tested; // [kMaxSearchBlocks] pairs examined per search workgroup
+    long long rows;
+    long long cells;
     int tiles_cells_n;
     int tiles_kept_n;
     size_t total_bytes;
@@ -97,11 +117,16 @@ struct Workspace {
 
 int64_t cells_max_for(int64_t n);
 int dpad_for(int d);
-Workspace layout(void *base, int64_t n, int d, int64_t edge_capacity);
+// Fills descs[e] (if not null) for events given by row offsets; returns the total
+// cell count.
+long long describe_events(const int64_t *event_offsets, int n_events, EventDesc *descs);
+// Workspace layout for events of the given sizes (host arithmetic; base may be null).
+Workspace layout(void *base, long long rows, long long cells, int n_events, int d, int64_t edge_capacity);
 
 struct LaunchArgs {
     const float *points;
-    int n;
+    int n_events;
+    int max_n;          // rows of the largest event
     int d;
     int dpad;
     int dims[3];
@@ -109,20 +134,22 @@ struct LaunchArgs {
     float r2;
     int K;
     int cell_div;
-    int tile;
-    int64_t cells_max;
     unsigned long long edge_capacity;
     long long *src;
     long long *dst;
     hipStream_t stream;
-    hipEvent_t *events;  // 9 events bracketing the 8 stages, or null
-    int search_blocks;   // resident workgroups of the search kernel
+    hipEvent_t *events;     // 9 events bracketing the 8 stages, or null
+    int search_blocks;      // resident workgroups of the search kernel
+    EventDesc ev0;          // event 0, written to ws.ev by the first kernel when ev_from_arg
+    int ev_from_arg;
+    long long *edge_off_out;  // device [n_events + 2] for the edge ranges and status, or null (workspace)
 };
 
-// Enqueues the whole pipeline on a.stream; the report lands in ws.report.
+// Enqueues the whole pipeline on a.stream; the report lands in ws.report and the
+// per-event edge ranges in ws.edge_off.
 hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws);
 
-// Resident workgroups of the search kernel for rows padded to dpad (per device).
+// Resident workgroups of the search kernel for rows padded to dpad (current device).
 int search_blocks_for(int dpad);
 
 }  // namespace frnn

@@ -139,24 +139,33 @@ struct BoundsAcc {
     }
 };
 
-__global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ X, int n, int d,
-                                                   int d0, int d1, int d2, int vec4,
-                                                   BoundsPartial *__restrict__ part,
-                                                   unsigned int *__restrict__ cell_count, int cells_max,
+// Grid (kBoundsBlocks, n_events): block (b, e) folds a share of event e's rows.
+// The first blocks also clear the histogram, tile totals and counters of the call.
+__global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ X, int d, int d0, int d1, int d2,
+                                                   int vec4, EventDesc *__restrict__ ev, EventDesc ev0,
+                                                   int ev_from_arg, BoundsPartial *__restrict__ part,
+                                                   unsigned int *__restrict__ cell_count, long long cells,
                                                    unsigned long long *__restrict__ sums_cells, int tiles_cells,
                                                    Counters *__restrict__ ctr) {
-    const int tid = blockIdx.x * kBlock + threadIdx.x;
-    const int stride = gridDim.x * kBlock;
-    for (int c = tid; c < cells_max; c += stride) cell_count[c] = 0u;
-    for (int c = tid; c < tiles_cells; c += stride) sums_cells[c] = 0ull;
-    if (tid == 0) {
+    const long long nblk = static_cast<long long>(gridDim.x) * gridDim.y;
+    const long long bid = static_cast<long long>(blockIdx.y) * gridDim.x + blockIdx.x;
+    const long long gtid = bid * kBlock + threadIdx.x;
+    const long long gstride = nblk * kBlock;
+    for (long long c = gtid; c < cells; c += gstride) cell_count[c] = 0u;
+    for (long long c = gtid; c < tiles_cells; c += gstride) sums_cells[c] = 0ull;
+    if (gtid == 0) {
         Counters z = {};
         *ctr = z;
+        if (ev_from_arg) ev[0] = ev0;
     }
+    const EventDesc E = ev_from_arg ? ev0 : ev[blockIdx.y];
+    const int tid = blockIdx.x * kBlock + threadIdx.x;
+    const int stride = gridDim.x * kBlock;
     BoundsAcc acc;
-    const long long total = static_cast<long long>(n) * d;
+    const long long total = static_cast<long long>(E.n) * d;
+    const float *Xe = X + static_cast<size_t>(E.row0) * d;
     if (vec4) {
-        const float4 *X4 = reinterpret_cast<const float4 *>(X);
+        const float4 *X4 = reinterpret_cast<const float4 *>(Xe);
         const long long nv = total / 4;
         for (long long v = tid; v < nv; v += stride) {
             const float4 x = X4[v];
@@ -170,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ X, 
             acc.add(x.w, col, d0, d1, d2);
         }
     } else {
-        for (long long e = tid; e < total; e += stride) acc.add(X[e], static_cast<int>(e % d), d0, d1, d2);
+        for (long long e = tid; e < total; e += stride) acc.add(Xe[e], static_cast<int>(e % d), d0, d1, d2);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -200,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ X, 
             out.nonfinite |= sp[w].nonfinite;
         }
         out.pad = 0;
-        part[blockIdx.x] = out;
+        part[static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x] = out;
     }
 }
 
@@ -287,38 +296,48 @@ __device__ __forceinline__ int cell_coord(float x, float lo, float inv_c, int G)
     return static_cast<int>(q);
 }
 
-constexpr int kMaxCellTiles = ((1 << 22) + 1 + kScanTile - 1) / kScanTile;
+constexpr int kMaxCellTiles = ((1 << 22) + kScanTile - 1) / kScanTile + 2;
 
-__global__ __launch_bounds__(kKeysBlock) void k_keys(const float *__restrict__ X, int n, int d,
-                                                 int d0, int d1, int d2, float r, int cell_div,
-                                                 int cells_max,
-                                                 const BoundsPartial *__restrict__ part, int nparts,
-                                                 Plan *__restrict__ plan_out,
-                                                 unsigned int *__restrict__ key,
-                                                 unsigned int *__restrict__ rank,
-                                                 unsigned int *__restrict__ cell_count,
-                                                 unsigned long long *__restrict__ sums_cells) {
+// Grid (blocks, n_events) of kKeysBlock threads: block 0 of event e derives and
+// stores its plan; every block computes keys of a share of the event's rows.
+__global__ __launch_bounds__(kKeysBlock) void k_keys(const float *__restrict__ X, int d, int d0, int d1, int d2,
+                                                     float r, int cell_div, const EventDesc *__restrict__ ev,
+                                                     const BoundsPartial *__restrict__ part, int nparts,
+                                                     Plan *__restrict__ plans, Counters *__restrict__ ctr,
+                                                     unsigned int *__restrict__ key,
+                                                     unsigned int *__restrict__ rank,
+                                                     unsigned int *__restrict__ cell_count,
+                                                     unsigned long long *__restrict__ sums_cells) {
     __shared__ Plan P;
     __shared__ unsigned int tile_count[kMaxCellTiles];
-    if (wave_id() == 0) derive_plan(part, nparts, r, cell_div, cells_max, &P);
-    const int ntiles = (cells_max + 1 + kScanTile - 1) / kScanTile;
+    const int e = blockIdx.y;
+    const EventDesc E = ev[e];
+    if (blockIdx.x != 0 && static_cast<long long>(blockIdx.x) * kKeysBlock >= E.n) return;
+    if (wave_id() == 0) derive_plan(part + static_cast<size_t>(e) * nparts, nparts, r, cell_div, E.cells_max, &P);
+    const int tile_end = static_cast<int>((E.cell0 + E.cells_max - 1) / kScanTile);
+    const int ntiles = tile_end - E.tile0 + 1;
     for (int t = threadIdx.x; t < ntiles; t += kKeysBlock) tile_count[t] = 0u;
     __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0) *plan_out = P;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        plans[e] = P;
+        if (P.abort) atomicOr(&ctr->abort, 1u);
+    }
     if (P.abort) return;
-    for (int i = blockIdx.x * kKeysBlock + threadIdx.x; i < n; i += gridDim.x * kKeysBlock) {
-        const float *row = X + static_cast<size_t>(i) * d;
+    for (int i = blockIdx.x * kKeysBlock + threadIdx.x; i < E.n; i += gridDim.x * kKeysBlock) {
+        const long long gi = E.row0 + i;
+        const float *row = X + static_cast<size_t>(gi) * d;
         const int u0 = cell_coord(row[d0], P.lo[0], P.inv_c[0], P.G[0]);
         const int u1 = cell_coord(row[d1], P.lo[1], P.inv_c[1], P.G[1]);
         const int u2 = cell_coord(row[d2], P.lo[2], P.inv_c[2], P.G[2]);
-        const unsigned int k = static_cast<unsigned int>((u2 * P.G[1] + u1) * P.G[0] + u0);
-        key[i] = k;
-        rank[i] = atomicAdd(&cell_count[k], 1u);
-        atomicAdd(&tile_count[k / kScanTile], 1u);
+        const unsigned int k = static_cast<unsigned int>(E.cell0) +
+                               static_cast<unsigned int>((u2 * P.G[1] + u1) * P.G[0] + u0);
+        key[gi] = k;
+        rank[gi] = atomicAdd(&cell_count[k], 1u);
+        atomicAdd(&tile_count[k / kScanTile - E.tile0], 1u);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ntiles; t += kKeysBlock)
-        if (tile_count[t]) atomicAdd(&sums_cells[t], static_cast<unsigned long long>(tile_count[t]));
+        if (tile_count[t]) atomicAdd(&sums_cells[E.tile0 + t], static_cast<unsigned long long>(tile_count[t]));
 }
 
 // ------------------------------------------------------------------- scans
@@ -326,12 +345,10 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(const float *__restrict__ X
 // out[i] = sum of in[0..i) for i in [0, len]; out[len] is the total.  sums[t] holds
 // the total of tile t (kScanTile elements).
 template <typename OutT>
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__restrict__ in,
-                                                       int host_len, const int *__restrict__ dev_len,
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__restrict__ in, long long len,
                                                        const unsigned long long *__restrict__ sums,
                                                        OutT *__restrict__ out) {
     __shared__ unsigned long long scratch[kWaves];
-    const long long len = dev_len ? *dev_len : host_len;
     const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
     if (base > len) return;
     unsigned long long off = 0;
@@ -363,12 +380,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X,
                                                     const unsigned int *__restrict__ key,
                                                     const unsigned int *__restrict__ rank,
                                                     const unsigned int *__restrict__ cell_start,
-                                                    const Plan *__restrict__ plan,
+                                                    const Counters *__restrict__ ctr,
                                                     float *__restrict__ sorted,
-                                                    unsigned int *__restrict__ sorted_id) {
-    if (plan->abort) return;
+                                                    unsigned int *__restrict__ sorted_id,
+                                                    unsigned int *__restrict__ sorted_key) {
+    if (ctr->abort) return;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const unsigned int slot = cell_start[key[i]] + rank[i];
+        const unsigned int ck = key[i];
+        const unsigned int slot = cell_start[ck] + rank[i];
         float row[DP];
         if (vec4) {
             const float4 *src = reinterpret_cast<const float4 *>(X + static_cast<size_t>(i) * d);
@@ -391,16 +410,29 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X,
         for (int k = 0; k < DP / 4; ++k)
             out[k] = make_float4(row[4 * k], row[4 * k + 1], row[4 * k + 2], row[4 * k + 3]);
         sorted_id[slot] = static_cast<unsigned int>(i);
+        sorted_key[slot] = ck;
     }
 }
 
 // ------------------------------------------------------------ neighbour runs
 
-// The neighbour cells of `cell` form (2R+1)^2 runs that are contiguous in cell
+// Event of a row: the last event whose first row is <= row (empty events share
+// their first row with the next event, so they are never returned for a row).
+__device__ __forceinline__ int find_event(const EventDesc *__restrict__ ev, int n_events, long long row) {
+    int lo = 0, hi = n_events - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ev[mid].row0 <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The neighbour cells of local cell `cell` (global keys start at cell0) form (2R+1)^2 runs that are contiguous in cell
 // order (x is the fastest axis).  Lane t < (2R+1)^2 builds run t: its first sorted
 // row (start) and the number of candidate rows before it (pre).  Returns the
 // candidate count, the same in every lane.  Call with the whole wave active.
-__device__ __forceinline__ unsigned int wave_runs(unsigned int cell, const Plan &P,
+__device__ __forceinline__ unsigned int wave_runs(unsigned int cell, unsigned int cell0, const Plan &P,
                                                   const unsigned int *__restrict__ cell_start,
                                                   unsigned int &start, unsigned int &pre) {
     const int G0 = P.G[0], G1 = P.G[1], G2 = P.G[2];
@@ -417,7 +449,7 @@ __device__ __forceinline__ unsigned int wave_runs(unsigned int cell, const Plan 
         const int zz = uz + (t / side) - R;
         if (yy >= 0 && yy < G1 && zz >= 0 && zz < G2) {
             const int xlo = max(ux - R, 0), xhi = min(ux + R, G0 - 1);
-            const unsigned int row = static_cast<unsigned int>((zz * G1 + yy) * G0);
+            const unsigned int row = cell0 + static_cast<unsigned int>((zz * G1 + yy) * G0);
             start = cell_start[row + xlo];
             len = cell_start[row + xhi + 1] - start;
         }
@@ -447,8 +479,10 @@ __device__ __forceinline__ unsigned int wave_candidate_row(unsigned int m, int n
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sorted,
                                                    const unsigned int *__restrict__ sorted_id,
+                                                   const unsigned int *__restrict__ sorted_key, int n,
+                                                   const EventDesc *__restrict__ ev, int n_events,
                                                    const unsigned int *__restrict__ cell_start,
-                                                   const Plan *__restrict__ plan, float r2, int K,
+                                                   const Plan *__restrict__ plans, float r2, int K,
                                                    unsigned int *__restrict__ kept,
                                                    unsigned long long *__restrict__ tpos,
                                                    unsigned int *__restrict__ temp,
@@ -456,36 +490,50 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
                                                    Counters *__restrict__ ctr,
                                                    unsigned long long *__restrict__ tested_out) {
     __shared__ unsigned int lst_all[kWaves][kQTile * kListCap];
+    __shared__ unsigned int pre_all[kWaves][kQTile + 1];
+    __shared__ unsigned int cnt_all[kWaves][kQTile];
     __shared__ unsigned long long tested_w[kWaves];
-    const Plan P = *plan;
-    if (P.abort) return;
+    if (ctr->abort) return;
     unsigned int *lst = lst_all[wave_id()];
+    unsigned int *tpre = pre_all[wave_id()];
+    unsigned int *tcnt = cnt_all[wave_id()];
     const int lane = lane_id();
-    const unsigned int n_cells = static_cast<unsigned int>(P.n_cells);
     const unsigned int total_waves = gridDim.x * kWaves;
-    const int side = 2 * P.reach + 1;
-    const int nruns = side * side;
     constexpr int kLead = DP < 3 ? DP : 3;  // terms before the first exact rejection test
     unsigned long long tested = 0;
 
     // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
-    // workgroups of one XCD take consecutive cells and share their rows in its L2.
-    // Each wave then takes one contiguous, equal share of the cells, so every XCD
-    // gets the same number of cells.
+    // workgroups of one XCD take consecutive queries and share their rows in its L2.
+    // Each wave takes an equal, contiguous share of the queries in cell order (a
+    // share may start or end inside a cell), so a dense cell is split across
+    // waves instead of holding up one wave.
     const unsigned int nb = gridDim.x;
     const unsigned int xcd = blockIdx.x % 8u, per = nb / 8u, rest = nb % 8u;
     const unsigned int lb = xcd < rest ? xcd * (per + 1u) + blockIdx.x / 8u
                                        : rest * (per + 1u) + (xcd - rest) * per + blockIdx.x / 8u;
     const unsigned int gw = lb * kWaves + wave_id();
-    const unsigned int cell_lo = static_cast<unsigned int>((static_cast<unsigned long long>(n_cells) * gw) / total_waves);
-    const unsigned int cell_hi =
-        static_cast<unsigned int>((static_cast<unsigned long long>(n_cells) * (gw + 1u)) / total_waves);
-    for (unsigned int cell = cell_lo; cell < cell_hi; ++cell) {
-        const unsigned int qs = uniform(cell_start[cell]);
-        const unsigned int qe = uniform(cell_start[cell + 1]);
-        if (qs != qe) {
+    const unsigned int q_lo = static_cast<unsigned int>((static_cast<unsigned long long>(n) * gw) / total_waves);
+    const unsigned int q_hi = static_cast<unsigned int>((static_cast<unsigned long long>(n) * (gw + 1u)) / total_waves);
+    int ev_cur = -1;
+    Plan P;
+    unsigned int cell0 = 0;
+    int nruns = 1;
+    for (unsigned int qa = q_lo; qa < q_hi;) {
+        const unsigned int cell = uniform(sorted_key[qa]);
+        const unsigned int qs = qa;
+        const unsigned int qe = min(uniform(cell_start[cell + 1]), q_hi);
+        qa = qe;
+        {
+            const int e = n_events == 1 ? 0 : find_event(ev, n_events, qs);
+            if (e != ev_cur) {
+                ev_cur = e;
+                P = plans[e];
+                cell0 = static_cast<unsigned int>(ev[e].cell0);
+                const int side = 2 * P.reach + 1;
+                nruns = side * side;
+            }
             unsigned int start, pre;
-            const unsigned int M = wave_runs(cell, P, cell_start, start, pre);
+            const unsigned int M = wave_runs(cell - cell0, cell0, P, cell_start, start, pre);
             for (unsigned int q0 = qs; q0 < qe; q0 += kQTile) {
                 const int Qn = static_cast<int>(min(static_cast<unsigned int>(kQTile), qe - q0));
                 unsigned int cnt = 0;  // lane q holds the hit count of query q0 + q
@@ -546,21 +594,43 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
                         he.slot = slot;
                         he.count = cnt;
                         he.cell = cell;
-                        he.pad = 0;
+                        he.event = static_cast<unsigned int>(ev_cur);
                         heavy[h] = he;
                         if (cnt > static_cast<unsigned int>(K)) atomicAdd(&ctr->capped, 1u);
                     }
                 }
-                // Sort each short list: lane t holds entry t, its rank is the number of
-                // smaller entries, read lane by lane (register reads, no LDS round trips).
-                for (int q = 0; q < Qn; ++q) {
-                    const unsigned int cq = __builtin_amdgcn_readlane(cnt, q);
-                    if (cq == 0u || cq > static_cast<unsigned int>(kListCap) || cq > static_cast<unsigned int>(K))
-                        continue;
-                    const unsigned int j = static_cast<unsigned int>(lane) < cq ? lst[q * kListCap + lane] : 0u;
-                    unsigned int rk = 0;
-                    for (unsigned int u = 0; u < cq; ++u) rk += __builtin_amdgcn_readlane(j, u) < j ? 1u : 0u;
-                    if (static_cast<unsigned int>(lane) < cq) temp[static_cast<size_t>(q0 + q) * kListCap + rk] = j;
+                // Sort the short lists together: the entries of all lists of the tile are
+                // numbered through a prefix over list lengths; each lane takes one entry,
+                // finds its query by binary search and its rank by counting the smaller
+                // entries of the same list.
+                {
+                    const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
+                                      cnt <= static_cast<unsigned int>(K);
+                    const unsigned int take = fits ? cnt : 0u;
+                    const unsigned int inc = wave_inclusive_scan(take);
+                    const unsigned int T = __builtin_amdgcn_readlane(inc, 63);
+                    if (lane < Qn) {
+                        tpre[lane] = inc - take;
+                        tcnt[lane] = take;
+                    }
+                    wave_lds_sync();
+                    for (unsigned int t0 = 0; t0 < T; t0 += 64) {
+                        const unsigned int t = t0 + lane;
+                        if (t < T) {
+                            int lo = 0, hi = Qn - 1;  // last query whose list starts at or before t
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (tpre[mid] <= t) lo = mid;
+                                else hi = mid - 1;
+                            }
+                            const unsigned int cq = tcnt[lo];
+                            const unsigned int *l = lst + lo * kListCap;
+                            const unsigned int j = l[t - tpre[lo]];
+                            unsigned int rk = 0;
+                            for (unsigned int u = 0; u < cq; ++u) rk += l[u] < j ? 1u : 0u;
+                            temp[static_cast<size_t>(q0 + lo) * kListCap + rk] = j;
+                        }
+                    }
                 }
                 wave_lds_sync();
             }
@@ -583,7 +653,8 @@ template <int DP>
 __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sorted,
                                                   const unsigned int *__restrict__ sorted_id,
                                                   const unsigned int *__restrict__ cell_start,
-                                                  const Plan *__restrict__ plan, float r2, int K, int n,
+                                                  const EventDesc *__restrict__ ev,
+                                                  const Plan *__restrict__ plans, float r2, int K, int n,
                                                   const unsigned int *__restrict__ kept,
                                                   unsigned long long *__restrict__ sums_kept, int tiles_kept,
                                                   unsigned long long *__restrict__ tpos,
@@ -601,8 +672,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
     __shared__ unsigned int remaining_s;
     __shared__ unsigned long long scratch[kWaves];
 
-    const Plan P = *plan;
-    if (P.abort) return;
+    if (ctr->abort) return;
 
     // Totals of kept counts per scan tile (kept is final for every query).
     for (int t = blockIdx.x; t < tiles_kept; t += gridDim.x) {
@@ -617,14 +687,16 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
     }
 
     const unsigned int n_heavy = ctr->heavy_count;
-    const int side = 2 * P.reach + 1;
-    const int nruns = side * side;
     for (unsigned int h = blockIdx.x; h < n_heavy; h += gridDim.x) {
         const HeavyEntry he = heavy[h];
+        const Plan P = plans[he.event];
+        const unsigned int cell0 = static_cast<unsigned int>(ev[he.event].cell0);
+        const int side = 2 * P.reach + 1;
+        const int nruns = side * side;
         for (int k = threadIdx.x; k < DP; k += kBlock) qv[k] = sorted[static_cast<size_t>(he.slot) * DP + k];
         if (wave_id() == 0) {
             unsigned int start, pre;
-            const unsigned int M = wave_runs(he.cell, P, cell_start, start, pre);
+            const unsigned int M = wave_runs(he.cell - cell0, cell0, P, cell_start, start, pre);
             run_start[lane_id()] = start;
             run_pre[lane_id()] = pre;
             if (lane_id() == 0) run_pre[64] = M;
@@ -728,80 +800,102 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
 
 // ------------------------------------------------------------------- place
 
-// Block b writes the edges of queries [256 b, 256 b + 256): each thread takes
-// output positions in turn and finds its query by binary search over the block's
-// offsets, so stores of src and dst are contiguous across the block.
-__global__ __launch_bounds__(kBlock) void k_place(int n, const unsigned long long *__restrict__ tpos,
-                                                  const long long *__restrict__ off,
-                                                  const unsigned int *__restrict__ temp,
-                                                  unsigned long long heavy_cap,
-                                                  long long *__restrict__ src, long long *__restrict__ dst,
-                                                  unsigned long long cap, const Plan *__restrict__ plan,
-                                                  const Counters *__restrict__ ctr,
-                                                  const unsigned long long *__restrict__ tested,
-                                                  int search_blocks, Report *__restrict__ report) {
-    __shared__ long long o[kBlock + 1];
-    __shared__ unsigned long long tp[kBlock];
-    __shared__ unsigned long long scratch[kWaves];
-    const Plan P = *plan;
-    const long long E = P.abort ? 0 : off[n];
+// Block b writes the edges of queries [256 b, 256 b + 256) with 1024 threads: each
+// thread takes output positions in turn and finds its query by binary search over
+// the block's offsets, so stores of src and dst are contiguous.  Indices are made
+// local to each query's event.  Block 0 also writes the report; the first threads
+// write every event's edge range, then a status word (0 ok, 2 non-finite input,
+// 3 more edges than capacity).
+__global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const EventDesc *__restrict__ ev,
+                                                       int n_events, const unsigned long long *__restrict__ tpos,
+                                                       const long long *__restrict__ off,
+                                                       const unsigned int *__restrict__ temp,
+                                                       unsigned long long heavy_cap,
+                                                       long long *__restrict__ src, long long *__restrict__ dst,
+                                                       unsigned long long cap, const Plan *__restrict__ plans,
+                                                       const Counters *__restrict__ ctr,
+                                                       const unsigned long long *__restrict__ tested,
+                                                       int search_blocks, long long *__restrict__ edge_off,
+                                                       Report *__restrict__ report) {
+    __shared__ long long o[kPlaceQueries + 1];
+    __shared__ unsigned long long tp[kPlaceQueries];
+    __shared__ long long base_row[kPlaceQueries];
+    __shared__ unsigned long long scratch[kPlaceBlock / 64];
+    const bool abort = ctr->abort != 0;
+    const long long E = abort ? 0 : off[rows];
     if (blockIdx.x == 0) {
         unsigned long long t = 0;
-        if (!P.abort)
-            for (int b = threadIdx.x; b < search_blocks; b += kBlock) t += tested[b];
-        t = block_sum(t, scratch);
+        if (!abort)
+            for (int b = threadIdx.x; b < search_blocks; b += kPlaceBlock) t += tested[b];
+        t = wave_sum(t);
+        if (lane_id() == 0) scratch[wave_id()] = t;
+        __syncthreads();
         if (threadIdx.x == 0) {
-        Report rep;
-        rep.n_edges = E;
-        rep.tested = t;
-        rep.abort = P.abort;
-        rep.capped = ctr->capped;
-        rep.heavy = ctr->heavy_count;
-        rep.n_cells = P.n_cells;
-        for (int p = 0; p < 3; ++p) {
-            rep.G[p] = P.G[p];
-            rep.c[p] = P.c[p];
-        }
-        *report = rep;
+            unsigned long long tt = 0;
+            for (int w = 0; w < kPlaceBlock / 64; ++w) tt += scratch[w];
+            const Plan P = plans[0];
+            Report rep;
+            rep.n_edges = E;
+            rep.tested = tt;
+            rep.abort = abort ? 1 : 0;
+            rep.capped = ctr->capped;
+            rep.heavy = ctr->heavy_count;
+            rep.n_cells = P.n_cells;
+            for (int p = 0; p < 3; ++p) {
+                rep.G[p] = P.G[p];
+                rep.c[p] = P.c[p];
+            }
+            *report = rep;
         }
     }
-    if (P.abort || static_cast<unsigned long long>(E) > cap || ctr->heavy_top > heavy_cap) return;
-    const int i0 = blockIdx.x * kBlock;
-    if (i0 >= n) return;
-    const int cnt = min(kBlock, n - i0);
-    for (int k = threadIdx.x; k <= cnt; k += kBlock) o[k] = off[i0 + k];
-    for (int k = threadIdx.x; k < cnt; k += kBlock) tp[k] = tpos[i0 + k];
+    const bool overflow = static_cast<unsigned long long>(E) > cap || ctr->heavy_top > heavy_cap;
+    for (long long e = static_cast<long long>(blockIdx.x) * kPlaceBlock + threadIdx.x; e <= n_events;
+         e += static_cast<long long>(gridDim.x) * kPlaceBlock)
+        edge_off[e] = abort ? 0 : off[e < n_events ? ev[e].row0 : rows];
+    if (blockIdx.x == 0 && threadIdx.x == 0) edge_off[n_events + 1] = abort ? 2 : (overflow ? 3 : 0);
+    if (abort || overflow) return;
+    const long long i0 = static_cast<long long>(blockIdx.x) * kPlaceQueries;
+    if (i0 >= rows) return;
+    const int cnt = static_cast<int>(rows - i0 < kPlaceQueries ? rows - i0 : kPlaceQueries);
+    for (int k = threadIdx.x; k <= cnt; k += kPlaceBlock) o[k] = off[i0 + k];
+    for (int k = threadIdx.x; k < cnt; k += kPlaceBlock) {
+        tp[k] = tpos[i0 + k];
+        base_row[k] = n_events == 1 ? 0 : ev[find_event(ev, n_events, i0 + k)].row0;
+    }
     __syncthreads();
     const long long first = o[0], last = o[cnt];
-    for (long long p = first + threadIdx.x; p < last; p += kBlock) {
+    for (long long p = first + threadIdx.x; p < last; p += kPlaceBlock) {
         int lo = 0, hi = cnt - 1;  // largest q with o[q] <= p
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (o[mid] <= p) lo = mid;
             else hi = mid - 1;
         }
-        src[p] = i0 + lo;
-        dst[p] = static_cast<long long>(temp[tp[lo] + static_cast<unsigned long long>(p - o[lo])]);
+        src[p] = i0 + lo - base_row[lo];
+        dst[p] = static_cast<long long>(temp[tp[lo] + static_cast<unsigned long long>(p - o[lo])]) - base_row[lo];
     }
 }
 
 // Launches the stages whose kernels depend on the padded row width.
 template <int DP>
-void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4, int gk) {
+void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     auto mark = [&](int stage) {
         if (a.events) (void)hipEventRecord(a.events[stage], a.stream);
     };
-    hipLaunchKernelGGL(k_scatter<DP>, dim3(gk), dim3(kBlock), 0, a.stream, a.points, a.n, a.d, vec4, ws.key,
-                       ws.rank, ws.cell_start, ws.plan, ws.sorted, ws.sorted_id);
+    const long long rows = ws.rows;
+    const long long nb = (rows + kBlock - 1) / kBlock;
+    const int gs = static_cast<int>(nb < 1 ? 1 : (nb > 8192 ? 8192 : nb));
+    hipLaunchKernelGGL(k_scatter<DP>, dim3(gs), dim3(kBlock), 0, a.stream, a.points, static_cast<int>(rows), a.d,
+                       vec4, ws.key, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id, ws.sorted_key);
     mark(4);
     hipLaunchKernelGGL(k_search<DP>, dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
-                       ws.cell_start, ws.plan, a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr,
-                       ws.tested);
+                       ws.sorted_key, static_cast<int>(rows), ws.ev, a.n_events, ws.cell_start, ws.plans, a.r2, a.K,
+                       ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested);
     mark(5);
-    const unsigned long long heavy_base = static_cast<unsigned long long>(a.n) * kListCap;
+    const unsigned long long heavy_base = static_cast<unsigned long long>(rows) * kListCap;
     hipLaunchKernelGGL(k_heavy<DP>, dim3(kHeavyBlocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
-                       ws.cell_start, ws.plan, a.r2, a.K, a.n, ws.kept, ws.sums_kept, ws.tiles_kept_n, ws.tpos,
-                       ws.temp, heavy_base, a.edge_capacity, ws.heavy, ws.ctr);
+                       ws.cell_start, ws.ev, ws.plans, a.r2, a.K, static_cast<int>(rows), ws.kept, ws.sums_kept,
+                       ws.tiles_kept_n, ws.tpos, ws.temp, heavy_base, a.edge_capacity, ws.heavy, ws.ctr);
 }
 
 template <int DP>
@@ -832,44 +926,45 @@ int search_blocks_for(int dpad) {
 }
 
 hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
-    const int cells_max = static_cast<int>(a.cells_max);
     auto mark = [&](int stage) {
         if (a.events) (void)hipEventRecord(a.events[stage], a.stream);
     };
     const int vec4 = (a.d % 4 == 0 && reinterpret_cast<uintptr_t>(a.points) % 16 == 0) ? 1 : 0;
-    const long long nb = (static_cast<long long>(a.n) + kBlock - 1) / kBlock;
-    const int gk = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
-    const long long nbk = (static_cast<long long>(a.n) + kKeysBlock - 1) / kKeysBlock;
-    const int gkeys = static_cast<int>(nbk < 1 ? 1 : (nbk > 1024 ? 1024 : nbk));
+    const long long kb = (static_cast<long long>(a.max_n) + kKeysBlock - 1) / kKeysBlock;
+    const int gkeys = static_cast<int>(kb < 1 ? 1 : (kb > 1024 ? 1024 : kb));
     mark(0);
-    hipLaunchKernelGGL(k_bounds, dim3(kBoundsBlocks), dim3(kBlock), 0, a.stream, a.points, a.n, a.d, a.dims[0],
-                       a.dims[1], a.dims[2], vec4, ws.part, ws.cell_count, cells_max, ws.sums_cells,
-                       ws.tiles_cells_n, ws.ctr);
+    hipLaunchKernelGGL(k_bounds, dim3(kBoundsBlocks, a.n_events), dim3(kBlock), 0, a.stream, a.points, a.d,
+                       a.dims[0], a.dims[1], a.dims[2], vec4, ws.ev, a.ev0, a.ev_from_arg, ws.part, ws.cell_count,
+                       ws.cells, ws.sums_cells, ws.tiles_cells_n, ws.ctr);
     mark(1);
-    hipLaunchKernelGGL(k_keys, dim3(gkeys), dim3(kKeysBlock), 0, a.stream, a.points, a.n, a.d, a.dims[0], a.dims[1],
-                       a.dims[2], a.r, a.cell_div, cells_max, ws.part, kBoundsBlocks, ws.plan, ws.key, ws.rank,
-                       ws.cell_count, ws.sums_cells);
+    hipLaunchKernelGGL(k_keys, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.points, a.d, a.dims[0],
+                       a.dims[1], a.dims[2], a.r, a.cell_div, ws.ev, ws.part, kBoundsBlocks, ws.plans, ws.ctr, ws.key,
+                       ws.rank, ws.cell_count, ws.sums_cells);
     mark(2);
     hipLaunchKernelGGL(k_scan_tiles<unsigned int>, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream,
-                       ws.cell_count, 0, &ws.plan->n_cells, ws.sums_cells, ws.cell_start);
+                       ws.cell_count, ws.cells, ws.sums_cells, ws.cell_start);
     mark(3);
     switch (a.dpad) {
-        case 4: launch_rows<4>(a, ws, vec4, gk); break;
-        case 8: launch_rows<8>(a, ws, vec4, gk); break;
-        case 12: launch_rows<12>(a, ws, vec4, gk); break;
-        case 16: launch_rows<16>(a, ws, vec4, gk); break;
-        case 24: launch_rows<24>(a, ws, vec4, gk); break;
-        case 32: launch_rows<32>(a, ws, vec4, gk); break;
-        case 48: launch_rows<48>(a, ws, vec4, gk); break;
-        default: launch_rows<64>(a, ws, vec4, gk); break;
+        case 4: launch_rows<4>(a, ws, vec4); break;
+        case 8: launch_rows<8>(a, ws, vec4); break;
+        case 12: launch_rows<12>(a, ws, vec4); break;
+        case 16: launch_rows<16>(a, ws, vec4); break;
+        case 24: launch_rows<24>(a, ws, vec4); break;
+        case 32: launch_rows<32>(a, ws, vec4); break;
+        case 48: launch_rows<48>(a, ws, vec4); break;
+        default: launch_rows<64>(a, ws, vec4); break;
     }
     mark(6);
-    hipLaunchKernelGGL(k_scan_tiles<long long>, dim3(ws.tiles_kept_n), dim3(kBlock), 0, a.stream, ws.kept, a.n,
-                       nullptr, ws.sums_kept, ws.off);
+    hipLaunchKernelGGL(k_scan_tiles<long long>, dim3(ws.tiles_kept_n), dim3(kBlock), 0, a.stream, ws.kept, ws.rows,
+                       ws.sums_kept, ws.off);
     mark(7);
-    hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(nb < 1 ? 1 : nb)), dim3(kBlock), 0, a.stream, a.n,
-                       ws.tpos, ws.off, ws.temp, a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plan, ws.ctr,
-                       ws.tested, a.search_blocks, ws.report);
+    const long long pb = (ws.rows + kPlaceQueries - 1) / kPlaceQueries;
+    const long long eb = (static_cast<long long>(a.n_events) + kPlaceBlock) / kPlaceBlock;
+    const long long gp = pb > eb ? pb : eb;
+    hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(gp < 1 ? 1 : gp)), dim3(kPlaceBlock), 0, a.stream,
+                       ws.rows, ws.ev, a.n_events, ws.tpos, ws.off, ws.temp, a.edge_capacity, a.src, a.dst,
+                       a.edge_capacity, ws.plans, ws.ctr, ws.tested, a.search_blocks,
+                       a.edge_off_out ? a.edge_off_out : ws.edge_off, ws.report);
     mark(8);
     return hipGetLastError();
 }

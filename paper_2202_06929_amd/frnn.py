@@ -13,6 +13,8 @@ import dataclasses
 import os
 import threading
 
+import numpy as np
+
 import torch  # loaded first so libfrnn binds to the HIP runtime PyTorch already uses
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -23,6 +25,7 @@ FRNN_ERR_WORKSPACE, FRNN_ERR_UNSUPPORTED, FRNN_ERR_HIP = 4, 5, 6
 MAX_D = 64
 MAX_K = 4096
 FLAG_TIMING = 1
+FLAG_EVENTS_RESIDENT = 2
 STAGES = ("bounds", "keys", "cells", "scatter", "search", "long", "offsets", "place")
 
 
@@ -59,6 +62,7 @@ class Config:
     cell_div: int = 1                           # cell edge = r (1 + 2^-10) / cell_div
     tile: int = 0
     timing: bool = False                        # per-stage HIP event timing in the stats
+    events_resident: bool = False               # batch event table already in the workspace
 
     def to_c(self) -> FrnnConfig:
         c = FrnnConfig()
@@ -67,7 +71,7 @@ class Config:
                 c.dims[p] = int(self.dims[p])
         c.cell_div = int(self.cell_div)
         c.tile = int(self.tile)
-        c.flags = FLAG_TIMING if self.timing else 0
+        c.flags = (FLAG_TIMING if self.timing else 0) | (FLAG_EVENTS_RESIDENT if self.events_resident else 0)
         return c
 
 
@@ -83,6 +87,15 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.frnn_build.argtypes = [vp, i64, i32, ctypes.c_float, i32, vp, ctypes.c_size_t, vp, vp, i64,
                                ctypes.POINTER(i64), ctypes.POINTER(FrnnConfig),
                                ctypes.POINTER(FrnnStats), vp]
+    lib.frnn_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.frnn_batch_workspace_bytes.argtypes = [ctypes.POINTER(i64), i32, i32, i64]
+    lib.frnn_build_batch.restype = ctypes.c_int
+    lib.frnn_build_batch.argtypes = [vp, ctypes.POINTER(i64), i32, i32, ctypes.c_float, i32, vp, ctypes.c_size_t,
+                                     vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(FrnnConfig),
+                                     ctypes.POINTER(FrnnStats), vp]
+    lib.frnn_build_batch_async.restype = ctypes.c_int
+    lib.frnn_build_batch_async.argtypes = [vp, ctypes.POINTER(i64), i32, i32, ctypes.c_float, i32, vp,
+                                           ctypes.c_size_t, vp, vp, i64, vp, ctypes.POINTER(FrnnConfig), vp]
     lib.frnn_status_string.restype = ctypes.c_char_p
     lib.frnn_status_string.argtypes = [ctypes.c_int]
     return lib
@@ -166,3 +179,86 @@ def build(points: torch.Tensor, r: float, K: int, config: Config | None = None,
             continue
         raise FrnnError(st, status_string(st))
     raise FrnnError(FRNN_ERR_CAPACITY, "capacity retry failed")
+
+
+def _offsets_array(offsets) -> np.ndarray:
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or off.size < 2:
+        raise ValueError("offsets must be int64 [n_events + 1]")
+    return off
+
+
+def batch_workspace_bytes(offsets, d: int, edge_capacity: int) -> int:
+    off = _offsets_array(offsets)
+    return int(lib().frnn_batch_workspace_bytes(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                                off.size - 1, d, edge_capacity))
+
+
+def build_batch_into(points: torch.Tensor, offsets, r: float, K: int, workspace: torch.Tensor,
+                     src: torch.Tensor, dst: torch.Tensor, config: Config | None = None,
+                     stats: FrnnStats | None = None) -> tuple[int, np.ndarray]:
+    """One call of frnn_build_batch on caller buffers.  Returns (status, edge_offsets)."""
+    off = _offsets_array(offsets)
+    n_events = off.size - 1
+    eo = np.zeros(n_events + 1, dtype=np.int64)
+    cfg = config.to_c() if config is not None else None
+    st = lib().frnn_build_batch(
+        ctypes.c_void_p(points.data_ptr()), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_events,
+        points.shape[1], ctypes.c_float(r), K, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+        ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(),
+        eo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(cfg) if cfg is not None else None,
+        ctypes.byref(stats) if stats is not None else None, ctypes.c_void_p(_stream_handle(points.device)))
+    return st, eo
+
+
+def build_batch(points: torch.Tensor, offsets, r: float, K: int, config: Config | None = None,
+                capacity: int | None = None, return_stats: bool = False):
+    """Edges of several events searched independently in one pass.
+
+    points holds the events' rows back to back; offsets (int64 [n_events + 1]) marks
+    where each event starts.  Returns (edges int64 [2, E], edge_offsets numpy int64
+    [n_events + 1]): event e's edges are edges[:, edge_offsets[e]:edge_offsets[e+1]],
+    with indices local to the event and sorted by (i, j).
+    """
+    _check_points(points)
+    off = _offsets_array(offsets)
+    d = points.shape[1]
+    rows = int(off[-1] - off[0])
+    cap = max(1, int(capacity)) if capacity is not None else max(1024, 16 * rows)
+    stats = FrnnStats()
+    for attempt in range(2):
+        wsb = batch_workspace_bytes(off, d, cap)
+        if wsb == 0:
+            raise FrnnError(FRNN_ERR_ARG, "invalid sizes")
+        ws = torch.empty(wsb, dtype=torch.uint8, device=points.device)
+        out = torch.empty((2, cap), dtype=torch.int64, device=points.device)
+        st, eo = build_batch_into(points, off, r, K, ws, out[0], out[1], config, stats)
+        if st == FRNN_OK:
+            edges = out[:, :int(eo[-1])]
+            return (edges, eo, stats.as_dict()) if return_stats else (edges, eo)
+        if st == FRNN_ERR_CAPACITY and attempt == 0:
+            cap = int(eo[-1])
+            continue
+        raise FrnnError(st, status_string(st))
+    raise FrnnError(FRNN_ERR_CAPACITY, "capacity retry failed")
+
+
+def build_batch_async(points: torch.Tensor, offsets, r: float, K: int, workspace: torch.Tensor,
+                      src: torch.Tensor, dst: torch.Tensor, edge_offsets: torch.Tensor,
+                      config: Config | None = None) -> int:
+    """Enqueues frnn_build_batch_async on the current stream and returns its status.
+
+    edge_offsets: device int64 [n_events + 2]; after the stream reaches this point it
+    holds the per-event edge ranges, the total, then a status word (0, 2 or 3).
+    """
+    off = _offsets_array(offsets)
+    n_events = off.size - 1
+    if edge_offsets.numel() < n_events + 2 or edge_offsets.dtype != torch.int64:
+        raise ValueError("edge_offsets must be a device int64 tensor of n_events + 2 entries")
+    cfg = config.to_c() if config is not None else None
+    return lib().frnn_build_batch_async(
+        ctypes.c_void_p(points.data_ptr()), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_events,
+        points.shape[1], ctypes.c_float(r), K, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+        ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(),
+        ctypes.c_void_p(edge_offsets.data_ptr()), ctypes.byref(cfg) if cfg is not None else None,
+        ctypes.c_void_p(_stream_handle(points.device)))

@@ -1,0 +1,112 @@
+"""Autotuner of the grid search: picks the cell size, the binned coordinates and the
+query tile for a workload by timing each candidate on a sample batch.
+
+Every candidate must return byte-identical edges (they are speed-only choices of
+the same exact search); the tuner checks that and refuses to pick otherwise.
+Choices are cached in a JSON file keyed by (GPU architecture, d, size bucket,
+r, K), so a workload is tuned once per machine.
+"""
+
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import frnn
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "frnn_mi355x_tune.json")
+
+
+def candidates(d: int) -> list[frnn.Config]:
+    """Cell divisions 1-3 crossed with three choices of binned coordinates: the last
+    three (leading terms of the distance sum unbinned, so the early exit bites), the
+    first three, and a spread of coordinates."""
+    dim_sets = [None, (0, 1, 2)]
+    if d >= 6:
+        dim_sets.append((d // 2, d // 2 + 1, d - 1))
+    out = []
+    for dims in dim_sets:
+        for div in (1, 2, 3):
+            out.append(frnn.Config(dims=dims, cell_div=div))
+    return out
+
+
+def size_bucket(rows: int) -> int:
+    return int(round(math.log2(max(rows, 1)) * 2))
+
+
+def cache_key(arch: str, d: int, rows: int, r: float, K: int) -> str:
+    return f"{arch}|d={d}|b={size_bucket(rows)}|r={r:.6g}|K={K}"
+
+
+def _arch() -> str:
+    props = torch.cuda.get_device_properties(0)
+    return getattr(props, "gcnArchName", props.name).split(":")[0]
+
+
+def _digest(edges: torch.Tensor) -> str:
+    return hashlib.sha256(edges.contiguous().cpu().numpy().tobytes()).hexdigest()
+
+
+def tune(points: torch.Tensor, offsets, r: float, K: int, repeats: int = 5,
+         cache_path: str | None = DEFAULT_CACHE, cands: list[frnn.Config] | None = None,
+         log=None) -> tuple[frnn.Config, dict]:
+    """Times every candidate on the batch (points, offsets); returns the fastest config
+    and a report {config: median seconds}.  Raises if candidates disagree."""
+    off = np.asarray(offsets, dtype=np.int64)
+    rows = int(off[-1] - off[0])
+    d = points.shape[1]
+    key = cache_key(_arch(), d, rows, r, K)
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            c = cache[key]
+            return frnn.Config(dims=tuple(c["dims"]) if c["dims"] else None, cell_div=c["cell_div"]), c
+    cands = cands or candidates(d)
+    _, eo0 = frnn.build_batch(points, off, r, K, config=cands[0])
+    cap = int(eo0[-1]) + 1024
+    ws_bytes = max(frnn.batch_workspace_bytes(off, d, cap), 1)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=points.device)
+    out = torch.empty((2, cap), dtype=torch.int64, device=points.device)
+    ref = None
+    timings = {}
+    for cfg in cands:
+        st, eo = frnn.build_batch_into(points, off, r, K, ws, out[0], out[1], cfg)
+        if st != frnn.FRNN_OK:
+            raise frnn.FrnnError(st, frnn.status_string(st))
+        digest = _digest(out[:, :int(eo[-1])])
+        if ref is None:
+            ref = (digest, eo.copy())
+        elif digest != ref[0] or not np.array_equal(eo, ref[1]):
+            raise AssertionError(f"config {cfg} changed the edges: the search is not exact")
+        ts = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            frnn.build_batch_into(points, off, r, K, ws, out[0], out[1], cfg)
+            ts.append(time.perf_counter() - t0)
+        timings[cfg] = float(np.median(ts))
+        if log:
+            log(f"tune {cfg}: {timings[cfg] * 1e3:.3f} ms")
+    best = min(timings, key=timings.get)
+    report = {"dims": list(best.dims) if best.dims else None, "cell_div": best.cell_div,
+              "seconds": timings[best], "key": key,
+              "all": {f"dims={c.dims} div={c.cell_div}": t for c, t in timings.items()}}
+    if cache_path:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        cache[key] = report
+        with open(cache_path + ".tmp", "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(cache_path + ".tmp", cache_path)
+    return best, report

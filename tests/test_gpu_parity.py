@@ -146,3 +146,77 @@ def test_invariants_on_the_high_occupancy_event():
     invariants.check(X[:0], spec.r, spec.K, np.zeros((2, 0), np.int64))
     deg = np.bincount(got[0], minlength=spec.n)
     assert deg.max() <= spec.K
+
+
+# ------------------------------------------------------------------ batches
+
+def _batch_case(seed=21):
+    """Events of uneven sizes (including empty and single-point ones) back to back."""
+    evs = [events.generate(events.TINY)[0]]
+    for k, n in enumerate((5000, 0, 1, 777, 12000, 2, 3001)):
+        spec = events.batched_spec(n, seed + k) if n >= 24 else None
+        if spec is None:
+            X = np.random.Generator(np.random.PCG64(seed + k)).uniform(-0.05, 0.05, size=(n, 8)).astype(np.float32)
+        else:
+            X, _ = events.generate(spec)
+        evs.append(X)
+    evs.append(next(c for c in events.stress_cases() if c.name == "S1_clump_cap").points)
+    return evs
+
+
+def test_batch_matches_each_event_alone():
+    evs = _batch_case()
+    offsets = np.concatenate([[0], np.cumsum([len(x) for x in evs])]).astype(np.int64)
+    pts = torch.from_numpy(np.concatenate(evs)).to(DEV)
+    log(f"batch of {len(evs)} events, {offsets[-1]} rows")
+    edges, eo = frnn.build_batch(pts, offsets, 0.1, 64)
+    edges = edges.cpu().numpy()
+    assert eo[0] == 0 and np.all(np.diff(eo) >= 0)
+    for e, X in enumerate(evs):
+        got = edges[:, eo[e]:eo[e + 1]]
+        assert_same(np.ascontiguousarray(got), oracle.frnn_grid(X, 0.1, 64))
+        if len(X):
+            alone = gpu_edges(X, 0.1, 64)
+            assert_same(np.ascontiguousarray(got), alone)
+
+
+def test_batch_capacity_and_nonfinite():
+    evs = _batch_case()
+    offsets = np.concatenate([[0], np.cumsum([len(x) for x in evs])]).astype(np.int64)
+    pts = torch.from_numpy(np.concatenate(evs)).to(DEV)
+    edges, eo = frnn.build_batch(pts, offsets, 0.1, 64, capacity=10)  # retries with the total needed
+    want_total = sum(oracle.frnn_grid(X, 0.1, 64).shape[1] for X in evs)
+    assert eo[-1] == want_total
+    bad = np.concatenate(evs)
+    bad[offsets[3] + 100 if offsets[4] - offsets[3] > 100 else offsets[1] + 5, 2] = np.nan
+    with pytest.raises(frnn.FrnnError) as e:
+        frnn.build_batch(torch.from_numpy(bad).to(DEV), offsets, 0.1, 64)
+    assert e.value.status == frnn.FRNN_ERR_NONFINITE
+
+
+def test_captured_batch_graph_replays_match_eager():
+    evs = _batch_case()
+    offsets = np.concatenate([[0], np.cumsum([len(x) for x in evs])]).astype(np.int64)
+    pts = torch.from_numpy(np.concatenate(evs)).to(DEV)
+    edges, eo = frnn.build_batch(pts, offsets, 0.1, 64)
+    eager = edges.cpu().numpy()
+    cap = int(eo[-1]) + 100
+    ws = torch.empty(frnn.batch_workspace_bytes(offsets, 8, cap), dtype=torch.uint8, device=DEV)
+    out = torch.empty((2, cap), dtype=torch.int64, device=DEV)
+    eo_dev = torch.zeros(len(evs) + 2, dtype=torch.int64, device=DEV)
+    assert frnn.build_batch_async(pts, offsets, 0.1, 64, ws, out[0], out[1], eo_dev) == frnn.FRNN_OK
+    torch.cuda.synchronize()
+    cfg = frnn.Config(events_resident=True)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        assert frnn.build_batch_async(pts, offsets, 0.1, 64, ws, out[0], out[1], eo_dev, cfg) == frnn.FRNN_OK
+    for rep in range(4):
+        out.fill_(-7)
+        eo_dev.fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        e_host = eo_dev.cpu().numpy()
+        assert e_host[-1] == 0, f"replay {rep}: status {e_host[-1]}"
+        assert np.array_equal(e_host[:-1], eo), f"replay {rep}: edge ranges differ"
+        assert_same(np.ascontiguousarray(out[:, :int(eo[-1])].cpu().numpy()), eager)
