@@ -176,6 +176,67 @@ def batched_bench(steps: int, warmup: int, log) -> dict:
             "tune": treport.get("all")}
 
 
+def served_bench(log, n_events: int = 300, load: float = 1.0) -> dict:
+    """Poisson arrivals of events with log-uniform hit counts in [10k, 300k].
+
+    The arrival rate is `load` times the plain loop's measured capacity (events/s
+    of one synchronous call per event).  The same trace runs through the plain loop
+    and through the continuous-batching server; a sample of served results is
+    checked byte-for-byte against the same event built alone.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2202_06929_amd import events, frnn, serve
+
+    r, K, d = 0.1, 256, 8
+    base = events.served_trace(n_events, rate_hz=1.0)
+    pts = [events.generate(events.batched_spec(n, 10_000 + k))[0] for k, (_, n) in enumerate(base)]
+    dev = torch.device("cuda:0")
+    dev_pts = [torch.from_numpy(x).to(dev) for x in pts]
+
+    def build(req):
+        return frnn.build(dev_pts[req.rid], r, K)
+
+    # Plain-loop capacity on these events (warm, back to back).
+    for k in range(5):
+        build(serve.Request(rid=k, arrival=0.0, points=pts[k]))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(n_events):
+        build(serve.Request(rid=k, arrival=0.0, points=pts[k]))
+    torch.cuda.synchronize()
+    capacity = n_events / (time.perf_counter() - t)
+    rate = load * capacity
+    arrivals = [a / rate for a, _ in base]  # the unit-rate trace scaled to the target rate
+
+    def trace():
+        return [serve.Request(rid=k, arrival=arrivals[k], points=pts[k]) for k in range(n_events)]
+
+    def idle(until):
+        while time.perf_counter() < until:
+            pass
+
+    plain_trace = trace()
+    plain = serve.plain_loop(plain_trace, build, idle=idle)
+    ex = serve.GpuExecutor(r, K, d, n_streams=3)
+    warm = serve.Server(ex, hbm_budget=64 << 30, max_batch=64, idle=idle)
+    warm.run(trace()[:20])
+    served_trace = trace()
+    srv = serve.Server(ex, hbm_budget=64 << 30, max_batch=64, idle=idle)
+    served = srv.run(served_trace)
+    for k in range(0, n_events, max(1, n_events // 10)):
+        a = served_trace[k].edges
+        b = plain_trace[k].edges
+        assert served_trace[k].status == serve.OK and torch.equal(a.cpu(), b.cpu()), f"served event {k} differs"
+    log(f"served: plain p50 {plain.p50_ms:.2f} p99 {plain.p99_ms:.2f} ms, {plain.events_per_s:.0f}/s; "
+        f"server p50 {served.p50_ms:.2f} p99 {served.p99_ms:.2f} ms, {served.events_per_s:.0f}/s")
+    return {"workload": f"served: {n_events} Poisson arrivals at {rate:.0f}/s ({load:.2f} x plain-loop capacity), "
+                        "hits log-uniform in [10000, 300000], 8-D float32, r=0.1, K=256, HBM budget 64 GB",
+            "plain_capacity_events_per_s": capacity, "plain": plain.as_dict(), "server": served.as_dict(),
+            "parity": "sampled served events identical to the same event alone"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -257,6 +318,8 @@ def main():
     }
     if not args.no_batched:
         result["batched"] = batched_bench(args.steps, args.warmup, log)
+    if not args.no_served:
+        result["served"] = served_bench(log)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(spec, X)
     print(json.dumps(result), flush=True)

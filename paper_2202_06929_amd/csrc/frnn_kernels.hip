@@ -479,7 +479,8 @@ __device__ __forceinline__ unsigned int wave_candidate_row(unsigned int m, int n
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sorted,
                                                    const unsigned int *__restrict__ sorted_id,
-                                                   const unsigned int *__restrict__ sorted_key, int n,
+                                                   const unsigned int *__restrict__ sorted_key, unsigned int q_base,
+                                                   unsigned int q_rem,
                                                    const EventDesc *__restrict__ ev, int n_events,
                                                    const unsigned int *__restrict__ cell_start,
                                                    const Plan *__restrict__ plans, float r2, int K,
@@ -512,8 +513,10 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
     const unsigned int lb = xcd < rest ? xcd * (per + 1u) + blockIdx.x / 8u
                                        : rest * (per + 1u) + (xcd - rest) * per + blockIdx.x / 8u;
     const unsigned int gw = lb * kWaves + wave_id();
-    const unsigned int q_lo = static_cast<unsigned int>((static_cast<unsigned long long>(n) * gw) / total_waves);
-    const unsigned int q_hi = static_cast<unsigned int>((static_cast<unsigned long long>(n) * (gw + 1u)) / total_waves);
+    // Shares of n / total_waves queries, the first n % total_waves waves one more
+    // (q_base and q_rem come from the host, so no division runs here).
+    const unsigned int q_lo = gw * q_base + min(gw, q_rem);
+    const unsigned int q_hi = q_lo + q_base + (gw < q_rem ? 1u : 0u);
     int ev_cur = -1;
     Plan P;
     unsigned int cell0 = 0;
@@ -889,7 +892,9 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
                        vec4, ws.key, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id, ws.sorted_key);
     mark(4);
     hipLaunchKernelGGL(k_search<DP>, dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
-                       ws.sorted_key, static_cast<int>(rows), ws.ev, a.n_events, ws.cell_start, ws.plans, a.r2, a.K,
+                       ws.sorted_key, static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves)),
+                       static_cast<unsigned int>(rows % (static_cast<long long>(a.search_blocks) * kWaves)), ws.ev,
+                       a.n_events, ws.cell_start, ws.plans, a.r2, a.K,
                        ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested);
     mark(5);
     const unsigned long long heavy_base = static_cast<unsigned long long>(rows) * kListCap;

@@ -103,3 +103,55 @@ def test_argument_errors_return_before_touching_a_device(lib):
     assert _call(lib, points=0x1000, ws=0x100000, wsb=16)[0] == frnn.FRNN_ERR_WORKSPACE
     # A workspace that is not 256-byte aligned is refused.
     assert _call(lib, points=0x1000, ws=0x100010, wsb=1 << 40)[0] == ERR
+
+
+def _batch_call(lib, offsets, n_events=None, d=8, r=0.1, K=4, ws=0, wsb=0, cap=0, eo=True):
+    import numpy as np
+    from paper_2202_06929_amd import frnn
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    n_events = off.size - 1 if n_events is None else n_events
+    out = np.zeros(max(n_events + 1, 1), dtype=np.int64)
+    return lib.frnn_build_batch(ctypes.c_void_p(0), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_events,
+                                d, ctypes.c_float(r), K, ctypes.c_void_p(ws), wsb, ctypes.c_void_p(0),
+                                ctypes.c_void_p(0), cap,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if eo else None, None, None,
+                                None)
+
+
+def test_batch_argument_errors_and_workspace_sizes(lib):
+    from paper_2202_06929_amd import frnn
+    ERR = frnn.FRNN_ERR_ARG
+    assert _batch_call(lib, [0, 10, 5]) == ERR          # decreasing offsets
+    assert _batch_call(lib, [0, 10], n_events=0) == ERR
+    assert _batch_call(lib, [0, 10], eo=False) == ERR
+    assert _batch_call(lib, [0, 10], d=2) == ERR
+    assert _batch_call(lib, [0, 10], K=0) == ERR
+    assert _batch_call(lib, [0, 0, 0]) == frnn.FRNN_OK  # no rows: nothing to do
+    assert _batch_call(lib, [0, 10, 20]) == ERR         # null points and workspace
+    assert _batch_call(lib, [0, 10, 20], ws=0x100000, wsb=16) == ERR  # points still null
+    one = frnn.batch_workspace_bytes([0, 1000], 8, 100)
+    assert one == frnn.workspace_bytes(1000, 8, 100)
+    two = frnn.batch_workspace_bytes([0, 1000, 3000], 8, 100)
+    assert two > frnn.batch_workspace_bytes([0, 2000], 8, 100) - 1 > one
+    assert frnn.batch_workspace_bytes([0, 5, 3], 8, 0) == 0
+    assert frnn.batch_workspace_bytes([0, 2 ** 31], 8, 0) == 0
+
+
+def test_distance_kernels_use_no_fused_or_packed_float_ops(tmp_path):
+    # Every product and sum of the distance is rounded on its own: the search and
+    # long-list kernels must contain no fused multiply-add and no packed FP32 op.
+    from paper_2202_06929_amd import build_lib
+    asm = open(build_lib.device_asm(str(tmp_path))).read()
+    kernels = re.split(r"\n(?=_ZN\S+:)", asm)
+    checked = 0
+    for body in kernels:
+        name = body.split(":", 1)[0]
+        if "k_search" not in name and "k_heavy" not in name:
+            continue
+        checked += 1
+        body = body.split(".Lfunc_end", 1)[0]
+        bad = re.findall(r"\b(v_fma\w*|v_fmac\w*|v_mad_f32\w*|v_mac_f32\w*|v_pk_fma\w*|v_pk_mul_f32|v_pk_add_f32)\b",
+                         body)
+        assert not bad, f"{name}: {sorted(set(bad))}"
+        assert re.search(r"\bv_(sub|subrev)_f32", body) and re.search(r"\bv_mul_f32", body)
+    assert checked >= 16
