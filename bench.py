@@ -200,18 +200,18 @@ def served_bench(log, n_events: int = 300, load: float = 1.0) -> dict:
 
     # Plain-loop capacity on these events (warm, back to back).
     for k in range(5):
-        build(serve.Request(rid=k, arrival=0.0, points=pts[k]))
+        build(serve.Request(rid=k, arrival=0.0, points=dev_pts[k]))
     torch.cuda.synchronize()
     t = time.perf_counter()
     for k in range(n_events):
-        build(serve.Request(rid=k, arrival=0.0, points=pts[k]))
+        build(serve.Request(rid=k, arrival=0.0, points=dev_pts[k]))
     torch.cuda.synchronize()
     capacity = n_events / (time.perf_counter() - t)
     rate = load * capacity
     arrivals = [a / rate for a, _ in base]  # the unit-rate trace scaled to the target rate
 
     def trace():
-        return [serve.Request(rid=k, arrival=arrivals[k], points=pts[k]) for k in range(n_events)]
+        return [serve.Request(rid=k, arrival=arrivals[k], points=dev_pts[k]) for k in range(n_events)]
 
     def idle(until):
         while time.perf_counter() < until:

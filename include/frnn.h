@@ -137,7 +137,7 @@ size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events
  * on its own: its own grid, no edges between events.
  *   points          device, float32, the events' rows back to back; event e is rows
  *                   [event_offsets[e], event_offsets[e+1]) of points (row-major, d columns)
- *   event_offsets   host, int64 [n_events + 1], non-decreasing; 1 <= n_events <= 65536;
+ *   event_offsets   host, int64 [n_events + 1], non-decreasing; 1 <= n_events <= 65535;
  *                   total rows < 2^31
  *   src, dst        device, int64 [edge_capacity] each: the events' edge lists back to back;
  *                   indices are local to their event (0 .. n_e - 1); each list sorted by (i, j)
@@ -166,6 +166,16 @@ int frnn_build_batch_async(const float *points, const int64_t *event_offsets, in
                            float r, int32_t K, void *workspace, size_t workspace_bytes,
                            int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *edge_offsets_device,
                            const frnn_config *config, void *stream);
+
+/* frnn_build_batch_async for events held in separate buffers: event e has
+ * event_sizes[e] rows at event_points[e] (device, row-major, d columns; a null
+ * pointer is allowed for an empty event).  event_points and event_sizes are host
+ * arrays of n_events entries.  The workspace size is frnn_batch_workspace_bytes of
+ * the offsets 0, s0, s0+s1, ...; outputs and status as for frnn_build_batch_async. */
+int frnn_build_events_async(const float *const *event_points, const int64_t *event_sizes, int32_t n_events,
+                            int32_t d, float r, int32_t K, void *workspace, size_t workspace_bytes,
+                            int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *edge_offsets_device,
+                            const frnn_config *config, void *stream);
 
 /* Static name of a status code. */
 const char *frnn_status_string(int status);

@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -75,7 +76,8 @@ int search_blocks_cached(int dpad) {
     return b;
 }
 
-thread_local Report *t_report = nullptr;  // pinned host copy of the device report
+thread_local Report *t_report = nullptr;    // pinned host copy of the device report
+thread_local Report *t_report_dev = nullptr;  // its device-visible address (null: copy instead)
 thread_local hipEvent_t t_events[FRNN_STAGES + 1] = {};
 thread_local bool t_events_ready = false;
 
@@ -87,6 +89,7 @@ long long describe_events(const int64_t *event_offsets, int n_events, EventDesc 
         const int64_t n = event_offsets[e + 1] - event_offsets[e];
         const int64_t cm = cells_max_for(n);
         if (descs) {
+            descs[e].pts = nullptr;
             descs[e].row0 = event_offsets[e] - event_offsets[0];
             descs[e].cell0 = cells;
             descs[e].n = static_cast<int>(n);
@@ -102,7 +105,7 @@ long long describe_events(const int64_t *event_offsets, int n_events, EventDesc 
 Workspace layout(void *base, long long rows, long long cells, int n_events, int d, int64_t edge_capacity) {
     const int dpad = dpad_for(d);
     const int64_t tiles_cells = (cells + 1 + kScanTile - 1) / kScanTile;
-    const int64_t tiles_kept = (rows + 1 + kScanTile - 1) / kScanTile;
+    const int64_t tiles_kept = rows > 0 ? (rows + kPlaceTile - 1) / kPlaceTile : 1;
     Carver cv{static_cast<char *>(base)};
     Workspace ws;
     ws.ev = cv.take<EventDesc>(n_events);
@@ -116,13 +119,14 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.cell_count = cv.take<unsigned int>(cells);
     ws.cell_start = cv.take<unsigned int>(cells + 1);
     ws.sums_cells = cv.take<unsigned long long>(tiles_cells);
+    const int64_t groups_kept = (tiles_kept + kKeptGroup - 1) / kKeptGroup;
     ws.sums_kept = cv.take<unsigned long long>(tiles_kept);
+    ws.sums_kept2 = cv.take<unsigned long long>(groups_kept);
     ws.sorted = cv.take<float>(static_cast<size_t>(rows) * dpad);
     ws.sorted_id = cv.take<unsigned int>(rows);
     ws.sorted_key = cv.take<unsigned int>(rows);
     ws.kept = cv.take<unsigned int>(rows);
     ws.tpos = cv.take<unsigned long long>(rows);
-    ws.off = cv.take<long long>(rows + 1);
     ws.heavy = cv.take<HeavyEntry>(rows);
     ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap + static_cast<size_t>(edge_capacity));
     ws.tested = cv.take<unsigned long long>(kMaxSearchBlocks);
@@ -130,6 +134,7 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.cells = cells;
     ws.tiles_cells_n = static_cast<int>(tiles_cells);
     ws.tiles_kept_n = static_cast<int>(tiles_kept);
+    ws.groups_kept_n = static_cast<int>(groups_kept);
     ws.total_bytes = cv.at;
     return ws;
 }
@@ -166,15 +171,17 @@ int check_events(const int64_t *event_offsets, int32_t n_events, long long *rows
 
 // Enqueues the pipeline for checked arguments (descriptors uploaded first unless
 // they are already resident).  Returns a status and the workspace view.
-int enqueue(const float *points, const EventDesc *descs, int n_events, long long rows, long long cells, int max_n,
+int enqueue(const EventDesc *descs, int n_events, long long rows, long long cells, int max_n,
             int32_t d, float r, int32_t K, void *workspace, int64_t *src, int64_t *dst, int64_t edge_capacity,
             const frnn_config *config, hipStream_t stream, bool upload, long long *edge_off_out, Workspace *ws_out,
-            bool *timing_out) {
+            bool *timing_out, Report *report_out = nullptr) {
     int dims[3] = {d - 3, d - 2, d - 1};
     if (config && config->dims[0] != config->dims[1])
         for (int p = 0; p < 3; ++p) dims[p] = config->dims[p];
     LaunchArgs a;
-    a.points = points;
+    a.vec4 = d % 4 == 0 ? 1 : 0;
+    for (int e = 0; e < n_events && a.vec4; ++e)
+        if (reinterpret_cast<uintptr_t>(descs[e].pts) % 16 != 0) a.vec4 = 0;
     a.n_events = n_events;
     a.max_n = max_n;
     a.d = d;
@@ -189,9 +196,13 @@ int enqueue(const float *points, const EventDesc *descs, int n_events, long long
     a.dst = reinterpret_cast<long long *>(dst);
     a.stream = stream;
     a.search_blocks = search_blocks_cached(a.dpad);
+    // About 16 coordinates per thread of the bounds pass, at most kBoundsBlocks blocks per event.
+    const long long bb = (static_cast<long long>(max_n) * d + 16 * kBlock - 1) / (16 * kBlock);
+    a.bounds_blocks = static_cast<int>(bb < 1 ? 1 : (bb > kBoundsBlocks ? kBoundsBlocks : bb));
     a.ev0 = descs ? descs[0] : EventDesc{};
     a.ev_from_arg = n_events == 1 ? 1 : 0;
     a.edge_off_out = edge_off_out;
+    a.report_out = report_out;
     const Workspace ws = layout(workspace, rows, cells, n_events, d, edge_capacity);
     const bool timing = config && (config->flags & FRNN_FLAG_TIMING);
     a.events = nullptr;
@@ -215,28 +226,39 @@ int enqueue(const float *points, const EventDesc *descs, int n_events, long long
 }
 
 // Enqueues, copies the report (and the per-event edge ranges) back and waits.
-int run(const float *points, const EventDesc *descs, int n_events, long long rows, long long cells, int max_n,
+int run(const EventDesc *descs, int n_events, long long rows, long long cells, int max_n,
         int32_t d, float r, int32_t K, void *workspace, int64_t *src, int64_t *dst, int64_t edge_capacity,
         const frnn_config *config, frnn_stats *stats, hipStream_t stream, Report *rep_out,
         int64_t *edge_offsets_host) {
+    // The last kernel writes the report straight into pinned host memory when the
+    // runtime maps it for the device; otherwise it is copied back.
     if (!t_report) {
         void *p = nullptr;
-        if (hipHostMalloc(&p, sizeof(Report), hipHostMallocDefault) != hipSuccess) return FRNN_ERR_HIP;
+        if (hipHostMalloc(&p, sizeof(Report), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+            if (hipHostMalloc(&p, sizeof(Report), hipHostMallocDefault) != hipSuccess) return FRNN_ERR_HIP;
+        } else {
+            void *dp = nullptr;
+            if (hipHostGetDevicePointer(&dp, p, 0) == hipSuccess) t_report_dev = static_cast<Report *>(dp);
+        }
         t_report = static_cast<Report *>(p);
     }
     Workspace ws;
     bool timing = false;
-    const int st = enqueue(points, descs, n_events, rows, cells, max_n, d, r, K, workspace, src, dst, edge_capacity,
-                           config, stream, true, nullptr, &ws, &timing);
+    t_report->n_edges = -1;
+    const int st = enqueue(descs, n_events, rows, cells, max_n, d, r, K, workspace, src, dst, edge_capacity,
+                           config, stream, true, nullptr, &ws, &timing, t_report_dev);
     if (st != FRNN_OK) return st;
-    if (hipMemcpyAsync(t_report, ws.report, sizeof(Report), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    if (!t_report_dev &&
+        hipMemcpyAsync(t_report, ws.report, sizeof(Report), hipMemcpyDeviceToHost, stream) != hipSuccess)
         return FRNN_ERR_HIP;
     if (edge_offsets_host &&
         hipMemcpyAsync(edge_offsets_host, ws.edge_off, sizeof(long long) * (n_events + 1), hipMemcpyDeviceToHost,
                        stream) != hipSuccess)
         return FRNN_ERR_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return FRNN_ERR_HIP;
-    *rep_out = *t_report;
+    std::atomic_thread_fence(std::memory_order_acquire);
+    memcpy(rep_out, t_report, sizeof(Report));
+    if (rep_out->n_edges < 0) return FRNN_ERR_HIP;  // the report never arrived
     if (stats) {
         stats->n_edges = rep_out->n_edges;
         stats->candidates = static_cast<int64_t>(rep_out->tested);
@@ -311,8 +333,9 @@ extern "C" int frnn_build(const float *points, int64_t n, int32_t d, float r, in
     const int64_t offs[2] = {0, n};
     EventDesc desc;
     const long long cells = describe_events(offs, 1, &desc);
+    desc.pts = points;
     Report rep;
-    const int rs = run(points, &desc, 1, n, cells, static_cast<int>(n), d, r, K, workspace, src, dst, edge_capacity,
+    const int rs = run(&desc, 1, n, cells, static_cast<int>(n), d, r, K, workspace, src, dst, edge_capacity,
                        config, stats, static_cast<hipStream_t>(stream), &rep, nullptr);
     if (rs == FRNN_OK || rs == FRNN_ERR_CAPACITY) *n_edges = rep.n_edges;
     return rs;
@@ -338,9 +361,9 @@ extern "C" int frnn_build_batch(const float *points, const int64_t *event_offset
         return FRNN_ERR_WORKSPACE;
     std::vector<EventDesc> descs(n_events);
     describe_events(event_offsets, n_events, descs.data());
+    for (int e = 0; e < n_events; ++e) descs[e].pts = points + static_cast<size_t>(event_offsets[e]) * d;
     Report rep;
-    const float *first = points + static_cast<size_t>(event_offsets[0]) * d;
-    const int rs = run(first, descs.data(), n_events, rows, cells, max_n, d, r, K, workspace, src, dst,
+    const int rs = run(descs.data(), n_events, rows, cells, max_n, d, r, K, workspace, src, dst,
                        edge_capacity, config, stats, static_cast<hipStream_t>(stream), &rep, edge_offsets);
     if (rs == FRNN_ERR_CAPACITY) {
         for (int e = 0; e < n_events; ++e) edge_offsets[e] = 0;
@@ -368,11 +391,45 @@ extern "C" int frnn_build_batch_async(const float *points, const int64_t *event_
         return FRNN_ERR_WORKSPACE;
     std::vector<EventDesc> descs(n_events);
     describe_events(event_offsets, n_events, descs.data());
+    for (int e = 0; e < n_events; ++e) descs[e].pts = points + static_cast<size_t>(event_offsets[e]) * d;
     const bool resident = config && (config->flags & FRNN_FLAG_EVENTS_RESIDENT);
     Workspace ws;
     bool timing = false;
-    const float *first = points + static_cast<size_t>(event_offsets[0]) * d;
-    return enqueue(first, descs.data(), n_events, rows, cells, max_n, d, r, K, workspace, src, dst, edge_capacity,
+    return enqueue(descs.data(), n_events, rows, cells, max_n, d, r, K, workspace, src, dst, edge_capacity,
                    config, static_cast<hipStream_t>(stream), !resident,
                    reinterpret_cast<long long *>(edge_offsets_device), &ws, &timing);
+}
+
+extern "C" int frnn_build_events_async(const float *const *event_points, const int64_t *event_sizes,
+                                       int32_t n_events, int32_t d, float r, int32_t K, void *workspace,
+                                       size_t workspace_bytes, int64_t *src, int64_t *dst, int64_t edge_capacity,
+                                       int64_t *edge_offsets_device, const frnn_config *config, void *stream) {
+    if (!edge_offsets_device || !event_points || !event_sizes || n_events < 1 || n_events > kMaxEvents)
+        return FRNN_ERR_ARG;
+    if (config && (config->flags & FRNN_FLAG_TIMING)) return FRNN_ERR_ARG;
+    const int st = check_common(d, r, K, edge_capacity, config);
+    if (st != FRNN_OK) return st;
+    std::vector<int64_t> offs(n_events + 1, 0);
+    for (int e = 0; e < n_events; ++e) {
+        if (event_sizes[e] < 0 || (event_sizes[e] > 0 && !event_points[e])) return FRNN_ERR_ARG;
+        offs[e + 1] = offs[e] + event_sizes[e];
+    }
+    long long rows = 0, cells = 0;
+    int max_n = 0;
+    const int se = check_events(offs.data(), n_events, &rows, &max_n, &cells);
+    if (se != FRNN_OK) return se;
+    if (rows == 0) return FRNN_ERR_ARG;
+    if (!workspace || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
+    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d, edge_capacity).total_bytes)
+        return FRNN_ERR_WORKSPACE;
+    std::vector<EventDesc> descs(n_events);
+    describe_events(offs.data(), n_events, descs.data());
+    for (int e = 0; e < n_events; ++e) descs[e].pts = event_points[e];
+    const bool resident = config && (config->flags & FRNN_FLAG_EVENTS_RESIDENT);
+    Workspace ws;
+    bool timing = false;
+    return enqueue(descs.data(), n_events, rows, cells, max_n, d, r, K, workspace, src, dst, edge_capacity, config,
+                   static_cast<hipStream_t>(stream), !resident, reinterpret_cast<long long *>(edge_offsets_device),
+                   &ws, &timing);
 }

@@ -10,7 +10,7 @@ namespace frnn {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kBoundsBlocks = 64;    // bounds partials per event
+constexpr int kBoundsBlocks = 256;   // most bounds partials per event
 constexpr int kScanTile = 4096;      // elements per workgroup in the scans
 constexpr int kListCap = 32;         // neighbours a query may collect in the main search
 constexpr int kQTile = 32;           // queries of one cell handled together by a wave
@@ -20,14 +20,17 @@ constexpr int kGridAxisMax = 1024;   // cells per binned axis (bounds the key ro
 constexpr int kMaxK = 4096;
 constexpr int kMaxSearchBlocks = 8192;
 constexpr int kKeysBlock = 1024;     // threads per workgroup of the key/histogram pass
-constexpr int kPlaceBlock = 1024;    // threads per workgroup of the placement pass
-constexpr int kPlaceQueries = 256;   // queries per workgroup of the placement pass
-constexpr int kMaxEvents = 1 << 16;
+constexpr int kPlaceBlock = 256;     // threads per workgroup of the placement pass
+constexpr int kPlaceTile = 256;      // queries per workgroup of the placement pass (and kept tile)
+constexpr int kKeptGroup = 64;       // kept tiles per second-level total
+constexpr int kOwnerWindow = 4096;   // output positions mapped to their query at a time in placement
+constexpr int kMaxEvents = 65535;  // events per call (the second grid dimension)
 
 // One event of a call: its rows in the concatenated points and its share of the
 // cell-key space.  The first event starts at row 0 and cell 0.
 struct EventDesc {
-    long long row0;    // first row of the event
+    const float *pts;  // the event's points (device, row-major [n, d])
+    long long row0;    // first row of the event in the call's row numbering
     long long cell0;   // first cell key of the event
     int n;             // rows of the event
     int cells_max;     // cells reserved for the event
@@ -98,13 +101,13 @@ struct Workspace {
     unsigned int *cell_count;   // [cells] histogram
     unsigned int *cell_start;   // [cells + 1] exclusive scan of the histogram
     unsigned long long *sums_cells;  // [tiles of cells + 1] per-tile histogram totals
-    unsigned long long *sums_kept;   // [tiles of rows + 1] per-tile kept totals
+    unsigned long long *sums_kept;   // [tiles of kPlaceTile rows] per-tile kept totals
+    unsigned long long *sums_kept2;  // [groups of kKeptGroup tiles] per-group kept totals
     float *sorted;              // [rows, dpad] points in cell order, zero-padded rows
     unsigned int *sorted_id;    // [rows] original row of each sorted row
     unsigned int *sorted_key;   // [rows] cell key of each sorted row
     unsigned int *kept;         // [rows] neighbours kept per original row
     unsigned long long *tpos;   // [rows] where each query's list sits in `temp`
-    long long *off;             // [rows + 1] exclusive scan of kept (output offsets)
     HeavyEntry *heavy;          // [rows]
     unsigned int *temp;         // [rows * kListCap + edge_capacity] neighbour lists
     unsigned long long *tested; // [kMaxSearchBlocks] pairs examined per search workgroup
@@ -112,6 +115,7 @@ struct Workspace {
     long long cells;
     int tiles_cells_n;
     int tiles_kept_n;
+    int groups_kept_n;
     size_t total_bytes;
 };
 
@@ -119,12 +123,13 @@ int64_t cells_max_for(int64_t n);
 int dpad_for(int d);
 // Fills descs[e] (if not null) for events given by row offsets; returns the total
 // cell count.
+// (pts stays null; callers set it).
 long long describe_events(const int64_t *event_offsets, int n_events, EventDesc *descs);
 // Workspace layout for events of the given sizes (host arithmetic; base may be null).
 Workspace layout(void *base, long long rows, long long cells, int n_events, int d, int64_t edge_capacity);
 
 struct LaunchArgs {
-    const float *points;
+    int vec4;           // every event's rows are 16-byte aligned float4 groups (d % 4 == 0)
     int n_events;
     int max_n;          // rows of the largest event
     int d;
@@ -140,9 +145,11 @@ struct LaunchArgs {
     hipStream_t stream;
     hipEvent_t *events;     // 9 events bracketing the 8 stages, or null
     int search_blocks;      // resident workgroups of the search kernel
+    int bounds_blocks;      // bounds partials per event (<= kBoundsBlocks)
     EventDesc ev0;          // event 0, written to ws.ev by the first kernel when ev_from_arg
     int ev_from_arg;
     long long *edge_off_out;  // device [n_events + 2] for the edge ranges and status, or null (workspace)
+    Report *report_out;       // device-visible pinned host report, or null (workspace)
 };
 
 // Enqueues the whole pipeline on a.stream; the report lands in ws.report and the

@@ -13,11 +13,11 @@
 //                 candidate row in registers, query rows are wave-uniform; an exact
 //                 early exit after the first three terms of the distance sum; wave
 //                 ballots collect hits; each list is sorted and stored
-//   k_heavy       per-tile kept totals; queries whose list is longer than the
-//                 search keeps, or longer than K: the K smallest by (D, j) found by
-//                 an MSB-first radix select
-//   k_scan_tiles  exclusive scan of kept counts -> int64 output offsets
-//   k_place       edges written to their (i asc, j asc) positions, coalesced
+//   k_heavy       kept totals per tile and per group of tiles; queries whose list
+//                 is longer than the search keeps, or longer than K: the K smallest
+//                 by (D, j) found by an MSB-first radix select
+//   k_place       output offsets from the totals and a block scan; edges written to
+//                 their (i asc, j asc) positions with coalesced stores
 //
 // Distances follow one fixed order with every product and sum rounded on its
 // own: this file is compiled with -ffp-contract=off and the pragma below.
@@ -37,7 +37,11 @@ __device__ __forceinline__ unsigned int prefix_count(unsigned long long mask) {
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+// Wave index inside the workgroup, marked wave-uniform for the compiler (so that
+// values derived from it live in scalar registers and feed scalar loads).
+__device__ __forceinline__ int wave_id() {
+    return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+}
 
 __device__ __forceinline__ unsigned int uniform(unsigned int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -55,6 +59,18 @@ __device__ __forceinline__ void wave_lds_sync() {
 // non-negative terms never decrease, so s >= r2 after a prefix rejects exactly.
 template <int K0, int K1, int DP>
 __device__ __forceinline__ float add_terms(float s, const float (&a)[DP], const float *__restrict__ b) {
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+        const float t = a[k] - b[k];
+        const float t2 = t * t;
+        s = s + t2;
+    }
+    return s;
+}
+
+// The same partial sum with the second row held in registers.
+template <int K0, int K1, int DP, int NB>
+__device__ __forceinline__ float add_terms_r(float s, const float (&a)[DP], const float (&b)[NB]) {
 #pragma unroll
     for (int k = K0; k < K1; ++k) {
         const float t = a[k] - b[k];
@@ -139,13 +155,14 @@ struct BoundsAcc {
     }
 };
 
-// Grid (kBoundsBlocks, n_events): block (b, e) folds a share of event e's rows.
+// Grid (bounds blocks, n_events): block (b, e) folds a share of event e's rows.
 // The first blocks also clear the histogram, tile totals and counters of the call.
-__global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ X, int d, int d0, int d1, int d2,
+__global__ __launch_bounds__(kBlock) void k_bounds(int d, int d0, int d1, int d2,
                                                    int vec4, EventDesc *__restrict__ ev, EventDesc ev0,
                                                    int ev_from_arg, BoundsPartial *__restrict__ part,
                                                    unsigned int *__restrict__ cell_count, long long cells,
                                                    unsigned long long *__restrict__ sums_cells, int tiles_cells,
+                                                   unsigned long long *__restrict__ sums_kept2, int groups_kept,
                                                    Counters *__restrict__ ctr) {
     const long long nblk = static_cast<long long>(gridDim.x) * gridDim.y;
     const long long bid = static_cast<long long>(blockIdx.y) * gridDim.x + blockIdx.x;
@@ -153,6 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ X, 
     const long long gstride = nblk * kBlock;
     for (long long c = gtid; c < cells; c += gstride) cell_count[c] = 0u;
     for (long long c = gtid; c < tiles_cells; c += gstride) sums_cells[c] = 0ull;
+    for (long long c = gtid; c < groups_kept; c += gstride) sums_kept2[c] = 0ull;
     if (gtid == 0) {
         Counters z = {};
         *ctr = z;
@@ -163,23 +181,48 @@ __global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ X, 
     const int stride = gridDim.x * kBlock;
     BoundsAcc acc;
     const long long total = static_cast<long long>(E.n) * d;
-    const float *Xe = X + static_cast<size_t>(E.row0) * d;
+    const float *Xe = E.pts;
+    // The column of a thread's element advances by a fixed step per stride, so it
+    // is tracked incrementally instead of a 64-bit remainder per element.
+    auto next_col = [d](int col, int step) {
+        col += step;
+        return col >= d ? col - d : col;
+    };
     if (vec4) {
         const float4 *X4 = reinterpret_cast<const float4 *>(Xe);
         const long long nv = total / 4;
-        for (long long v = tid; v < nv; v += stride) {
+        const int step = static_cast<int>((4ll * stride) % d);
+        int col = static_cast<int>((4ll * tid) % d);
+        long long v = tid;
+        // Four independent loads in flight per thread.
+        for (; v + 3ll * stride < nv; v += 4ll * stride) {
+            float4 x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = X4[v + u * static_cast<long long>(stride)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc.add(x[u].x, col, d0, d1, d2);
+                acc.add(x[u].y, col + 1, d0, d1, d2);
+                acc.add(x[u].z, col + 2, d0, d1, d2);
+                acc.add(x[u].w, col + 3, d0, d1, d2);
+                col = next_col(col, step);
+            }
+        }
+        for (; v < nv; v += stride) {
             const float4 x = X4[v];
-            int col = static_cast<int>((4 * v) % d);
             acc.add(x.x, col, d0, d1, d2);
-            col = col + 1 == d ? 0 : col + 1;
-            acc.add(x.y, col, d0, d1, d2);
-            col = col + 1 == d ? 0 : col + 1;
-            acc.add(x.z, col, d0, d1, d2);
-            col = col + 1 == d ? 0 : col + 1;
-            acc.add(x.w, col, d0, d1, d2);
+            acc.add(x.y, col + 1, d0, d1, d2);
+            acc.add(x.z, col + 2, d0, d1, d2);
+            acc.add(x.w, col + 3, d0, d1, d2);
+            col = next_col(col, step);
         }
     } else {
-        for (long long e = tid; e < total; e += stride) acc.add(Xe[e], static_cast<int>(e % d), d0, d1, d2);
+        const int step = stride % d;
+        int col = tid % d;
+        for (long long e = tid; e < total; e += stride) {
+            acc.add(Xe[e], col, d0, d1, d2);
+            col = next_col(col, step);
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -300,7 +343,7 @@ constexpr int kMaxCellTiles = ((1 << 22) + kScanTile - 1) / kScanTile + 2;
 
 // Grid (blocks, n_events) of kKeysBlock threads: block 0 of event e derives and
 // stores its plan; every block computes keys of a share of the event's rows.
-__global__ __launch_bounds__(kKeysBlock) void k_keys(const float *__restrict__ X, int d, int d0, int d1, int d2,
+__global__ __launch_bounds__(kKeysBlock) void k_keys(int d, int d0, int d1, int d2,
                                                      float r, int cell_div, const EventDesc *__restrict__ ev,
                                                      const BoundsPartial *__restrict__ part, int nparts,
                                                      Plan *__restrict__ plans, Counters *__restrict__ ctr,
@@ -313,6 +356,17 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(const float *__restrict__ X
     const int e = blockIdx.y;
     const EventDesc E = ev[e];
     if (blockIdx.x != 0 && static_cast<long long>(blockIdx.x) * kKeysBlock >= E.n) return;
+    // One point per thread; its binned coordinates are loaded before the plan is
+    // derived so that the two latencies overlap.
+    const int i = blockIdx.x * kKeysBlock + threadIdx.x;
+    const bool live = i < E.n;
+    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    if (live) {
+        const float *row = E.pts + static_cast<size_t>(i) * d;
+        x0 = row[d0];
+        x1 = row[d1];
+        x2 = row[d2];
+    }
     if (wave_id() == 0) derive_plan(part + static_cast<size_t>(e) * nparts, nparts, r, cell_div, E.cells_max, &P);
     const int tile_end = static_cast<int>((E.cell0 + E.cells_max - 1) / kScanTile);
     const int ntiles = tile_end - E.tile0 + 1;
@@ -323,12 +377,11 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(const float *__restrict__ X
         if (P.abort) atomicOr(&ctr->abort, 1u);
     }
     if (P.abort) return;
-    for (int i = blockIdx.x * kKeysBlock + threadIdx.x; i < E.n; i += gridDim.x * kKeysBlock) {
+    if (live) {
         const long long gi = E.row0 + i;
-        const float *row = X + static_cast<size_t>(gi) * d;
-        const int u0 = cell_coord(row[d0], P.lo[0], P.inv_c[0], P.G[0]);
-        const int u1 = cell_coord(row[d1], P.lo[1], P.inv_c[1], P.G[1]);
-        const int u2 = cell_coord(row[d2], P.lo[2], P.inv_c[2], P.G[2]);
+        const int u0 = cell_coord(x0, P.lo[0], P.inv_c[0], P.G[0]);
+        const int u1 = cell_coord(x1, P.lo[1], P.inv_c[1], P.G[1]);
+        const int u2 = cell_coord(x2, P.lo[2], P.inv_c[2], P.G[2]);
         const unsigned int k = static_cast<unsigned int>(E.cell0) +
                                static_cast<unsigned int>((u2 * P.G[1] + u1) * P.G[0] + u0);
         key[gi] = k;
@@ -375,8 +428,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__res
 
 // ----------------------------------------------------------------- scatter
 
+// Grid (blocks, n_events): block (b, e) copies a share of event e's rows.
 template <int DP>
-__global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X, int n, int d, int vec4,
+__global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const EventDesc *__restrict__ ev,
                                                     const unsigned int *__restrict__ key,
                                                     const unsigned int *__restrict__ rank,
                                                     const unsigned int *__restrict__ cell_start,
@@ -385,12 +439,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X,
                                                     unsigned int *__restrict__ sorted_id,
                                                     unsigned int *__restrict__ sorted_key) {
     if (ctr->abort) return;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const unsigned int ck = key[i];
-        const unsigned int slot = cell_start[ck] + rank[i];
+    const EventDesc E = ev[blockIdx.y];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < E.n; i += gridDim.x * kBlock) {
+        const long long gi = E.row0 + i;
+        const unsigned int ck = key[gi];
+        const unsigned int slot = cell_start[ck] + rank[gi];
         float row[DP];
         if (vec4) {
-            const float4 *src = reinterpret_cast<const float4 *>(X + static_cast<size_t>(i) * d);
+            const float4 *src = reinterpret_cast<const float4 *>(E.pts + static_cast<size_t>(i) * d);
 #pragma unroll
             for (int k = 0; k < DP / 4; ++k) {
                 float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -401,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X,
                 row[4 * k + 3] = v.w;
             }
         } else {
-            const float *src = X + static_cast<size_t>(i) * d;
+            const float *src = E.pts + static_cast<size_t>(i) * d;
 #pragma unroll
             for (int k = 0; k < DP; ++k) row[k] = k < d ? src[k] : 0.0f;
         }
@@ -409,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const float *__restrict__ X,
 #pragma unroll
         for (int k = 0; k < DP / 4; ++k)
             out[k] = make_float4(row[4 * k], row[4 * k + 1], row[4 * k + 2], row[4 * k + 3]);
-        sorted_id[slot] = static_cast<unsigned int>(i);
+        sorted_id[slot] = static_cast<unsigned int>(gi);
         sorted_key[slot] = ck;
     }
 }
@@ -466,7 +522,7 @@ __device__ __forceinline__ unsigned int wave_candidate_row(unsigned int m, int n
                                                            unsigned int pre) {
     int r = 0;
     for (int t = 1; t < nruns; ++t) {
-        const unsigned int p = uniform(static_cast<unsigned int>(__shfl(pre, t)));
+        const unsigned int p = __builtin_amdgcn_readlane(pre, t);  // t is wave-uniform
         r += (m >= p) ? 1 : 0;
     }
     const unsigned int s0 = static_cast<unsigned int>(__shfl(start, r));
@@ -501,6 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
     const int lane = lane_id();
     const unsigned int total_waves = gridDim.x * kWaves;
     constexpr int kLead = DP < 3 ? DP : 3;  // terms before the first exact rejection test
+    constexpr int kPre = DP < 16 ? DP : 16;  // coordinates of a query row held in registers
     unsigned long long tested = 0;
 
     // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
@@ -561,13 +618,26 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
                     const unsigned int s = sn, jid = jn;
                     if (base + 64 < M) fetch(base + 64);
                     const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
+                    // Query rows are wave-uniform (scalar loads); the next one is
+                    // requested before the current one is tested.
+                    float qn[kPre];
+#pragma unroll
+                    for (int k = 0; k < kPre; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
                     for (int q = 0; q < Qn; ++q) {
                         const unsigned int qslot = q0 + q;
                         const float *qrow = sorted + static_cast<size_t>(qslot) * DP;
-                        float acc = add_terms<0, kLead, DP>(0.0f, c, qrow);
+                        float qc[kPre];
+#pragma unroll
+                        for (int k = 0; k < kPre; ++k) qc[k] = qn[k];
+                        if (q + 1 < Qn) {
+#pragma unroll
+                            for (int k = 0; k < kPre; ++k) qn[k] = qrow[DP + k];
+                        }
+                        float acc = add_terms_r<0, kLead, DP, kPre>(0.0f, c, qc);
                         const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2) & vmask;
                         if (m1 == 0ull) continue;
-                        acc = add_terms<kLead, DP, DP>(acc, c, qrow);
+                        acc = add_terms_r<kLead, kPre, DP, kPre>(acc, c, qc);
+                        acc = add_terms<kPre, DP, DP>(acc, c, qrow);
                         const unsigned long long m2 = __builtin_amdgcn_ballot_w64(acc < r2) & vmask &
                                                       ~__builtin_amdgcn_ballot_w64(s == qslot);
                         if (m2 == 0ull) continue;
@@ -659,7 +729,8 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
                                                   const EventDesc *__restrict__ ev,
                                                   const Plan *__restrict__ plans, float r2, int K, int n,
                                                   const unsigned int *__restrict__ kept,
-                                                  unsigned long long *__restrict__ sums_kept, int tiles_kept,
+                                                  unsigned long long *__restrict__ sums_kept,
+                                                  unsigned long long *__restrict__ sums_kept2, int tiles_kept,
                                                   unsigned long long *__restrict__ tpos,
                                                   unsigned int *__restrict__ temp,
                                                   unsigned long long heavy_base, unsigned long long heavy_cap,
@@ -677,16 +748,24 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
 
     if (ctr->abort) return;
 
-    // Totals of kept counts per scan tile (kept is final for every query).
-    for (int t = blockIdx.x; t < tiles_kept; t += gridDim.x) {
-        unsigned long long s = 0;
-        const long long b = static_cast<long long>(t) * kScanTile;
-        for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
-            const long long idx = b + k;
-            if (idx < n) s += kept[idx];
+    // Totals of kept counts (final for every query) per placement tile, one wave
+    // per tile, and per group of kKeptGroup tiles (spread-address atomics).
+    {
+        const int nw = static_cast<int>(gridDim.x) * kWaves;
+        for (int t = static_cast<int>(blockIdx.x) * kWaves + wave_id(); t < tiles_kept; t += nw) {
+            const long long b = static_cast<long long>(t) * kPlaceTile;
+            unsigned long long s = 0;
+#pragma unroll
+            for (int k = 0; k < kPlaceTile / 64; ++k) {
+                const long long idx = b + k * 64 + lane_id();
+                if (idx < n) s += kept[idx];
+            }
+            s = wave_sum(s);
+            if (lane_id() == 0) {
+                sums_kept[t] = s;
+                if (s) atomicAdd(&sums_kept2[t / kKeptGroup], s);
+            }
         }
-        s = block_sum(s, scratch);
-        if (threadIdx.x == 0) sums_kept[t] = s;
     }
 
     const unsigned int n_heavy = ctr->heavy_count;
@@ -803,15 +882,19 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
 
 // ------------------------------------------------------------------- place
 
-// Block b writes the edges of queries [256 b, 256 b + 256) with 1024 threads: each
-// thread takes output positions in turn and finds its query by binary search over
-// the block's offsets, so stores of src and dst are contiguous.  Indices are made
-// local to each query's event.  Block 0 also writes the report; the first threads
-// write every event's edge range, then a status word (0 ok, 2 non-finite input,
-// 3 more edges than capacity).
+// Block b owns queries [kPlaceTile b, kPlaceTile (b + 1)), one per thread.  Its
+// first output position is the sum of the kept totals before it (whole groups of
+// kKeptGroup tiles, then the tiles of its own group); a block scan of its kept
+// counts gives each query's offset.  Output positions are then mapped to their
+// query through an owner table in LDS, a window at a time, so that consecutive
+// threads write consecutive int64 positions.  Indices are made local to each
+// query's event.  Block 0 writes the report and the status; the block holding an
+// event's first row writes its edge offset.
 __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const EventDesc *__restrict__ ev,
-                                                       int n_events, const unsigned long long *__restrict__ tpos,
-                                                       const long long *__restrict__ off,
+                                                       int n_events, const unsigned int *__restrict__ kept,
+                                                       const unsigned long long *__restrict__ sums_kept,
+                                                       const unsigned long long *__restrict__ sums_kept2,
+                                                       int groups_kept, const unsigned long long *__restrict__ tpos,
                                                        const unsigned int *__restrict__ temp,
                                                        unsigned long long heavy_cap,
                                                        long long *__restrict__ src, long long *__restrict__ dst,
@@ -820,26 +903,39 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                                                        const unsigned long long *__restrict__ tested,
                                                        int search_blocks, long long *__restrict__ edge_off,
                                                        Report *__restrict__ report) {
-    __shared__ long long o[kPlaceQueries + 1];
-    __shared__ unsigned long long tp[kPlaceQueries];
-    __shared__ long long base_row[kPlaceQueries];
-    __shared__ unsigned long long scratch[kPlaceBlock / 64];
+    static_assert(kPlaceBlock == kPlaceTile && kPlaceTile <= 256, "one query per thread, owner ids fit a byte");
+    __shared__ unsigned int o[kPlaceTile + 1];
+    __shared__ unsigned long long tp[kPlaceTile];
+    __shared__ unsigned int base_row[kPlaceTile];
+    __shared__ unsigned char owner[kOwnerWindow];
+    __shared__ unsigned long long scratch[kWaves];
     const bool abort = ctr->abort != 0;
-    const long long E = abort ? 0 : off[rows];
-    if (blockIdx.x == 0) {
+    const int b = static_cast<int>(blockIdx.x);
+    const int g = b / kKeptGroup;
+    unsigned long long pre = 0, tot = 0;
+    if (!abort) {
+        for (int t = threadIdx.x; t < groups_kept; t += kPlaceBlock) {
+            const unsigned long long v = sums_kept2[t];
+            tot += v;
+            if (t < g) pre += v;
+        }
+        const int t = g * kKeptGroup + static_cast<int>(threadIdx.x);
+        if (threadIdx.x < kKeptGroup && t < b) pre += sums_kept[t];
+    }
+    pre = block_sum(pre, scratch);
+    tot = block_sum(tot, scratch);
+    const long long E = static_cast<long long>(tot);
+    const bool overflow = static_cast<unsigned long long>(E) > cap || ctr->heavy_top > heavy_cap;
+    if (b == 0) {
         unsigned long long t = 0;
         if (!abort)
-            for (int b = threadIdx.x; b < search_blocks; b += kPlaceBlock) t += tested[b];
-        t = wave_sum(t);
-        if (lane_id() == 0) scratch[wave_id()] = t;
-        __syncthreads();
+            for (int k = threadIdx.x; k < search_blocks; k += kPlaceBlock) t += tested[k];
+        t = block_sum(t, scratch);
         if (threadIdx.x == 0) {
-            unsigned long long tt = 0;
-            for (int w = 0; w < kPlaceBlock / 64; ++w) tt += scratch[w];
             const Plan P = plans[0];
             Report rep;
             rep.n_edges = E;
-            rep.tested = tt;
+            rep.tested = t;
             rep.abort = abort ? 1 : 0;
             rep.capped = ctr->capped;
             rep.heavy = ctr->heavy_count;
@@ -849,33 +945,57 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                 rep.c[p] = P.c[p];
             }
             *report = rep;
+            edge_off[n_events] = E;
+            edge_off[n_events + 1] = abort ? 2 : (overflow ? 3 : 0);
         }
     }
-    const bool overflow = static_cast<unsigned long long>(E) > cap || ctr->heavy_top > heavy_cap;
-    for (long long e = static_cast<long long>(blockIdx.x) * kPlaceBlock + threadIdx.x; e <= n_events;
-         e += static_cast<long long>(gridDim.x) * kPlaceBlock)
-        edge_off[e] = abort ? 0 : off[e < n_events ? ev[e].row0 : rows];
-    if (blockIdx.x == 0 && threadIdx.x == 0) edge_off[n_events + 1] = abort ? 2 : (overflow ? 3 : 0);
-    if (abort || overflow) return;
-    const long long i0 = static_cast<long long>(blockIdx.x) * kPlaceQueries;
-    if (i0 >= rows) return;
-    const int cnt = static_cast<int>(rows - i0 < kPlaceQueries ? rows - i0 : kPlaceQueries);
-    for (int k = threadIdx.x; k <= cnt; k += kPlaceBlock) o[k] = off[i0 + k];
-    for (int k = threadIdx.x; k < cnt; k += kPlaceBlock) {
-        tp[k] = tpos[i0 + k];
-        base_row[k] = n_events == 1 ? 0 : ev[find_event(ev, n_events, i0 + k)].row0;
-    }
+    const long long i0 = static_cast<long long>(b) * kPlaceTile;
+    const int cnt = static_cast<int>(rows - i0 < kPlaceTile ? rows - i0 : kPlaceTile);
+    const int q = threadIdx.x;
+    const unsigned int kq = (!abort && q < cnt) ? kept[i0 + q] : 0u;
+    const unsigned int oq = static_cast<unsigned int>(block_exclusive_scan(kq, scratch));
+    if (q < cnt) o[q] = oq;
+    if (q == cnt - 1) o[cnt] = oq + kq;
     __syncthreads();
-    const long long first = o[0], last = o[cnt];
-    for (long long p = first + threadIdx.x; p < last; p += kPlaceBlock) {
-        int lo = 0, hi = cnt - 1;  // largest q with o[q] <= p
+    // Edge ranges of the events whose first row lies in this block (events with no
+    // rows at the very end start at E).
+    {
+        int lo = 0, hi = n_events;  // first event whose first row is >= i0
         while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (o[mid] <= p) lo = mid;
-            else hi = mid - 1;
+            const int mid = (lo + hi) >> 1;
+            if (ev[mid].row0 < i0) lo = mid + 1;
+            else hi = mid;
         }
-        src[p] = i0 + lo - base_row[lo];
-        dst[p] = static_cast<long long>(temp[tp[lo] + static_cast<unsigned long long>(p - o[lo])]) - base_row[lo];
+        const bool last_block = b == static_cast<int>(gridDim.x) - 1;
+        for (int e = lo + threadIdx.x; e < n_events; e += kPlaceBlock) {
+            const long long r0 = ev[e].row0;
+            if (r0 >= i0 + cnt && !(last_block && r0 >= rows)) break;
+            edge_off[e] = abort ? 0 : (r0 >= rows ? E : static_cast<long long>(pre + o[r0 - i0]));
+        }
+    }
+    if (abort || overflow) return;
+    if (q < cnt) {
+        tp[q] = tpos[i0 + q];
+        base_row[q] = n_events == 1 ? 0u : static_cast<unsigned int>(ev[find_event(ev, n_events, i0 + q)].row0);
+    }
+    const unsigned int total = o[cnt];
+    if (pre + total > cap) return;  // cannot happen when E <= cap; never write past the outputs
+    for (unsigned int w0 = 0; w0 < total; w0 += kOwnerWindow) {
+        const unsigned int wend = total - w0 < kOwnerWindow ? total - w0 : kOwnerWindow;
+        if (q < cnt) {
+            const unsigned int a0 = oq > w0 ? oq - w0 : 0u;
+            const unsigned int a1 = oq + kq > w0 ? min(oq + kq - w0, wend) : 0u;
+            for (unsigned int p = a0; p < a1; ++p) owner[p] = static_cast<unsigned char>(q);
+        }
+        __syncthreads();
+        for (unsigned int p = threadIdx.x; p < wend; p += kPlaceBlock) {
+            const int r = owner[p];
+            const unsigned int pos = w0 + p;
+            const long long out = static_cast<long long>(pre) + pos;
+            src[out] = i0 + r - base_row[r];
+            dst[out] = static_cast<long long>(temp[tp[r] + (pos - o[r])]) - base_row[r];
+        }
+        __syncthreads();
     }
 }
 
@@ -886,10 +1006,10 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
         if (a.events) (void)hipEventRecord(a.events[stage], a.stream);
     };
     const long long rows = ws.rows;
-    const long long nb = (rows + kBlock - 1) / kBlock;
-    const int gs = static_cast<int>(nb < 1 ? 1 : (nb > 8192 ? 8192 : nb));
-    hipLaunchKernelGGL(k_scatter<DP>, dim3(gs), dim3(kBlock), 0, a.stream, a.points, static_cast<int>(rows), a.d,
-                       vec4, ws.key, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id, ws.sorted_key);
+    const long long nb = (static_cast<long long>(a.max_n) + kBlock - 1) / kBlock;
+    const int gs = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
+    hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, ws.key,
+                       ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id, ws.sorted_key);
     mark(4);
     hipLaunchKernelGGL(k_search<DP>, dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
                        ws.sorted_key, static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves)),
@@ -898,9 +1018,12 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
                        ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested);
     mark(5);
     const unsigned long long heavy_base = static_cast<unsigned long long>(rows) * kListCap;
-    hipLaunchKernelGGL(k_heavy<DP>, dim3(kHeavyBlocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
+    const long long hb = (static_cast<long long>(ws.tiles_kept_n) + kWaves - 1) / kWaves;
+    const int heavy_blocks = static_cast<int>(hb < kHeavyBlocks ? kHeavyBlocks : (hb > 2048 ? 2048 : hb));
+    hipLaunchKernelGGL(k_heavy<DP>, dim3(heavy_blocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
                        ws.cell_start, ws.ev, ws.plans, a.r2, a.K, static_cast<int>(rows), ws.kept, ws.sums_kept,
-                       ws.tiles_kept_n, ws.tpos, ws.temp, heavy_base, a.edge_capacity, ws.heavy, ws.ctr);
+                       ws.sums_kept2, ws.tiles_kept_n, ws.tpos, ws.temp, heavy_base, a.edge_capacity, ws.heavy,
+                       ws.ctr);
 }
 
 template <int DP>
@@ -934,16 +1057,16 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
     auto mark = [&](int stage) {
         if (a.events) (void)hipEventRecord(a.events[stage], a.stream);
     };
-    const int vec4 = (a.d % 4 == 0 && reinterpret_cast<uintptr_t>(a.points) % 16 == 0) ? 1 : 0;
+    const int vec4 = a.vec4;
     const long long kb = (static_cast<long long>(a.max_n) + kKeysBlock - 1) / kKeysBlock;
-    const int gkeys = static_cast<int>(kb < 1 ? 1 : (kb > 1024 ? 1024 : kb));
+    const int gkeys = static_cast<int>(kb < 1 ? 1 : kb);  // one point per thread
     mark(0);
-    hipLaunchKernelGGL(k_bounds, dim3(kBoundsBlocks, a.n_events), dim3(kBlock), 0, a.stream, a.points, a.d,
+    hipLaunchKernelGGL(k_bounds, dim3(a.bounds_blocks, a.n_events), dim3(kBlock), 0, a.stream, a.d,
                        a.dims[0], a.dims[1], a.dims[2], vec4, ws.ev, a.ev0, a.ev_from_arg, ws.part, ws.cell_count,
-                       ws.cells, ws.sums_cells, ws.tiles_cells_n, ws.ctr);
+                       ws.cells, ws.sums_cells, ws.tiles_cells_n, ws.sums_kept2, ws.groups_kept_n, ws.ctr);
     mark(1);
-    hipLaunchKernelGGL(k_keys, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.points, a.d, a.dims[0],
-                       a.dims[1], a.dims[2], a.r, a.cell_div, ws.ev, ws.part, kBoundsBlocks, ws.plans, ws.ctr, ws.key,
+    hipLaunchKernelGGL(k_keys, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.d, a.dims[0],
+                       a.dims[1], a.dims[2], a.r, a.cell_div, ws.ev, ws.part, a.bounds_blocks, ws.plans, ws.ctr, ws.key,
                        ws.rank, ws.cell_count, ws.sums_cells);
     mark(2);
     hipLaunchKernelGGL(k_scan_tiles<unsigned int>, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream,
@@ -960,16 +1083,13 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
         default: launch_rows<64>(a, ws, vec4); break;
     }
     mark(6);
-    hipLaunchKernelGGL(k_scan_tiles<long long>, dim3(ws.tiles_kept_n), dim3(kBlock), 0, a.stream, ws.kept, ws.rows,
-                       ws.sums_kept, ws.off);
     mark(7);
-    const long long pb = (ws.rows + kPlaceQueries - 1) / kPlaceQueries;
-    const long long eb = (static_cast<long long>(a.n_events) + kPlaceBlock) / kPlaceBlock;
-    const long long gp = pb > eb ? pb : eb;
-    hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(gp < 1 ? 1 : gp)), dim3(kPlaceBlock), 0, a.stream,
-                       ws.rows, ws.ev, a.n_events, ws.tpos, ws.off, ws.temp, a.edge_capacity, a.src, a.dst,
-                       a.edge_capacity, ws.plans, ws.ctr, ws.tested, a.search_blocks,
-                       a.edge_off_out ? a.edge_off_out : ws.edge_off, ws.report);
+    hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
+                       ws.rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n, ws.tpos,
+                       ws.temp,
+                       a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, ws.tested,
+                       a.search_blocks, a.edge_off_out ? a.edge_off_out : ws.edge_off,
+                       a.report_out ? a.report_out : ws.report);
     mark(8);
     return hipGetLastError();
 }

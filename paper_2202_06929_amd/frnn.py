@@ -96,6 +96,10 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.frnn_build_batch_async.restype = ctypes.c_int
     lib.frnn_build_batch_async.argtypes = [vp, ctypes.POINTER(i64), i32, i32, ctypes.c_float, i32, vp,
                                            ctypes.c_size_t, vp, vp, i64, vp, ctypes.POINTER(FrnnConfig), vp]
+    lib.frnn_build_events_async.restype = ctypes.c_int
+    lib.frnn_build_events_async.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(i64), i32, i32,
+                                            ctypes.c_float, i32, vp, ctypes.c_size_t, vp, vp, i64, vp,
+                                            ctypes.POINTER(FrnnConfig), vp]
     lib.frnn_status_string.restype = ctypes.c_char_p
     lib.frnn_status_string.argtypes = [ctypes.c_int]
     return lib
@@ -262,3 +266,28 @@ def build_batch_async(points: torch.Tensor, offsets, r: float, K: int, workspace
         ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(),
         ctypes.c_void_p(edge_offsets.data_ptr()), ctypes.byref(cfg) if cfg is not None else None,
         ctypes.c_void_p(_stream_handle(points.device)))
+
+
+def build_events_async(event_points: list[torch.Tensor], r: float, K: int, workspace: torch.Tensor,
+                       src: torch.Tensor, dst: torch.Tensor, edge_offsets: torch.Tensor,
+                       config: Config | None = None) -> int:
+    """Enqueues frnn_build_events_async for events held in separate device tensors.
+
+    The workspace size is batch_workspace_bytes of the events' cumulative sizes;
+    edge_offsets (device int64 [n_events + 2]) receives the ranges and the status.
+    """
+    if not event_points:
+        raise ValueError("no events")
+    d = event_points[0].shape[1]
+    for p in event_points:
+        if p.dtype != torch.float32 or p.dim() != 2 or p.shape[1] != d or not p.is_contiguous():
+            raise TypeError("every event must be a contiguous float32 tensor [n, d]")
+    n_events = len(event_points)
+    ptrs = (ctypes.c_void_p * n_events)(*[p.data_ptr() if p.shape[0] else 0 for p in event_points])
+    sizes = np.array([p.shape[0] for p in event_points], dtype=np.int64)
+    cfg = config.to_c() if config is not None else None
+    return lib().frnn_build_events_async(
+        ptrs, sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_events, d, ctypes.c_float(r), K,
+        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.c_void_p(src.data_ptr()),
+        ctypes.c_void_p(dst.data_ptr()), src.numel(), ctypes.c_void_p(edge_offsets.data_ptr()),
+        ctypes.byref(cfg) if cfg is not None else None, ctypes.c_void_p(_stream_handle(event_points[0].device)))

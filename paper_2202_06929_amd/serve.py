@@ -28,7 +28,7 @@ OK, REJECTED, FAILED = 0, -1, -2
 class Request:
     rid: int
     arrival: float              # seconds on the server clock
-    points: np.ndarray          # float32 [n, d], host
+    points: object              # float32 [n, d]: a numpy array or a device tensor
     admitted: float | None = None
     started: float | None = None
     done: float | None = None
@@ -199,12 +199,12 @@ def plain_loop(trace: list[Request], build: Callable[[Request], object],
 
 
 class GpuExecutor:
-    """Runs batches through frnn_build_batch_async on a few streams.
+    """Runs batches through frnn_build_events_async on a few streams.
 
-    Each request's points are pinned and uploaded when it is admitted; a batch
-    gathers them into one device buffer on its stream, runs the whole pipeline
-    there and records an event.  Outputs and workspaces come from PyTorch's caching
-    allocator and stay on the device until the request is released.
+    Requests hold their points on the device already (the embedding stage that
+    produces them runs on the GPU).  A batch passes the events' device pointers to
+    the library, which searches each event on its own grid; outputs and workspaces
+    come from PyTorch's caching allocator and stay on the device until released.
     """
 
     def __init__(self, r: float, K: int, d: int, n_streams: int = 3, config=None, edges_per_point: int = 16,
@@ -219,23 +219,14 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.busy = [False] * n_streams
-        self.uploads: dict[int, object] = {}
 
     def footprint(self, req: Request) -> int:
         n = max(req.n, 1)
         offs = np.array([0, n], dtype=np.int64)
-        return int(self.frnn.batch_workspace_bytes(offs, self.d, self.epp * n)) + n * self.d * 4 + 16 * self.epp * n
+        return int(self.frnn.batch_workspace_bytes(offs, self.d, self.epp * n)) + 16 * self.epp * n
 
     def admit(self, req: Request) -> None:
-        torch = self.torch
-        host = torch.from_numpy(np.ascontiguousarray(req.points, dtype=np.float32)).pin_memory()
-        dev = torch.empty(host.shape, dtype=torch.float32, device=self.device)
-        s = self.streams[req.rid % len(self.streams)]
-        with torch.cuda.stream(s):
-            dev.copy_(host, non_blocking=True)
-        ev = torch.cuda.Event()
-        ev.record(s)
-        self.uploads[req.rid] = (host, dev, ev)
+        pass
 
     def free_streams(self) -> int:
         return self.busy.count(False)
@@ -248,18 +239,14 @@ class GpuExecutor:
         offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         rows = int(offsets[-1])
         cap = max(1024, self.epp * rows)
+        s.wait_stream(torch.cuda.current_stream(self.device))  # the points were produced there
         with torch.cuda.stream(s):
-            for req in batch:
-                s.wait_event(self.uploads[req.rid][2])
-            pts = torch.empty((max(rows, 1), self.d), dtype=torch.float32, device=self.device)
-            for req, a, b in zip(batch, offsets[:-1], offsets[1:]):
-                if b > a:
-                    pts[int(a):int(b)].copy_(self.uploads[req.rid][1], non_blocking=True)
             ws = torch.empty(frnn.batch_workspace_bytes(offsets, self.d, cap), dtype=torch.uint8, device=self.device)
             out = torch.empty((2, cap), dtype=torch.int64, device=self.device)
             eo = torch.empty(len(batch) + 2, dtype=torch.int64, device=self.device)
             if rows > 0:
-                st = frnn.build_batch_async(pts, offsets, self.r, self.K, ws, out[0], out[1], eo, self.config)
+                st = frnn.build_events_async([req.points for req in batch], self.r, self.K, ws, out[0], out[1],
+                                             eo, self.config)
                 if st != frnn.FRNN_OK:
                     raise frnn.FrnnError(st, frnn.status_string(st))
             else:
@@ -267,8 +254,7 @@ class GpuExecutor:
             done = torch.cuda.Event()
             done.record(s)
         self.busy[k] = True
-        return {"stream": k, "event": done, "out": out, "eo": eo, "offsets": offsets, "batch": batch,
-                "keep": (pts, ws)}
+        return {"stream": k, "event": done, "out": out, "eo": eo, "batch": batch, "ws": ws}
 
     def poll(self, handle) -> bool:
         return handle["event"].query()
@@ -279,14 +265,12 @@ class GpuExecutor:
         eo = handle["eo"].cpu().numpy()
         batch = handle["batch"]
         status = int(eo[-1])
-        if status == 3:  # more edges than the guess: rerun this batch with the exact total
-            edges, eo2 = frnn.build_batch(handle["keep"][0][:int(handle["offsets"][-1])], handle["offsets"],
-                                          self.r, self.K, self.config, capacity=int(eo[-2]))
-            return [(OK, edges[:, int(eo2[k]):int(eo2[k + 1])]) for k in range(len(batch))]
+        if status == 3:  # more edges than the guess: rebuild each event with exact room
+            return [(OK, frnn.build(req.points, self.r, self.K, self.config)) for req in batch]
         if status != 0:
             return [(status, None) for _ in batch]
         out = handle["out"]
         return [(OK, out[:, int(eo[k]):int(eo[k + 1])]) for k in range(len(batch))]
 
     def release(self, req: Request) -> None:
-        self.uploads.pop(req.rid, None)
+        pass

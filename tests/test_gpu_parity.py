@@ -220,3 +220,42 @@ def test_captured_batch_graph_replays_match_eager():
         assert e_host[-1] == 0, f"replay {rep}: status {e_host[-1]}"
         assert np.array_equal(e_host[:-1], eo), f"replay {rep}: edge ranges differ"
         assert_same(np.ascontiguousarray(out[:, :int(eo[-1])].cpu().numpy()), eager)
+
+
+def test_events_entry_point_matches_oracle():
+    """frnn_build_events_async with each event in its own allocation (no gather)."""
+    evs = _batch_case()
+    tensors = [torch.from_numpy(np.ascontiguousarray(X)).to(DEV) for X in evs]
+    offsets = np.concatenate([[0], np.cumsum([len(x) for x in evs])]).astype(np.int64)
+    want = [oracle.frnn_grid(X, 0.1, 64) for X in evs]
+    cap = sum(w.shape[1] for w in want) + 64
+    ws = torch.empty(frnn.batch_workspace_bytes(offsets, 8, cap), dtype=torch.uint8, device=DEV)
+    out = torch.full((2, cap), -7, dtype=torch.int64, device=DEV)
+    eo = torch.full((len(evs) + 2,), -1, dtype=torch.int64, device=DEV)
+    log(f"events entry point: {len(evs)} events")
+    assert frnn.build_events_async(tensors, 0.1, 64, ws, out[0], out[1], eo) == frnn.FRNN_OK
+    torch.cuda.synchronize()
+    eo = eo.cpu().numpy()
+    assert eo[-1] == 0
+    got = out.cpu().numpy()
+    for e in range(len(evs)):
+        assert_same(np.ascontiguousarray(got[:, eo[e]:eo[e + 1]]), want[e])
+
+
+def test_served_requests_match_oracle():
+    """The continuous-batching server on the GPU: every request's edges equal the oracle's."""
+    from paper_2202_06929_amd import serve
+
+    spec = events.batched_spec(1, 0)
+    reqs = []
+    host = []
+    for k, (t, n) in enumerate(events.served_trace(24, 20000.0, lo=200, hi=15000, seed=5)):
+        X, _ = events.generate(events.batched_spec(n, 1000 + k))
+        host.append(X)
+        reqs.append(serve.Request(rid=k, arrival=t, points=torch.from_numpy(X).to(DEV)))
+    ex = serve.GpuExecutor(spec.r, spec.K, host[0].shape[1], n_streams=3)
+    stats = serve.Server(ex, hbm_budget=8 << 30, max_batch=8).run(reqs)
+    log(f"served: {stats}")
+    assert stats.completed == len(reqs)
+    for req, X in zip(reqs, host):
+        assert_same(np.ascontiguousarray(req.edges.cpu().numpy()), oracle.frnn_grid(X, spec.r, spec.K))
