@@ -12,8 +12,9 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kBoundsBlocks = 256;   // most bounds partials per event
 constexpr int kScanTile = 4096;      // elements per workgroup in the scans
-constexpr int kListCap = 32;         // neighbours a query may collect in the main search
+constexpr int kListCap = 16;         // neighbours a query may collect in the main search
 constexpr int kQTile = 32;           // queries of one cell handled together by a wave
+constexpr int kRing = 128;           // first-stage survivors queued per wave (a power of two)
 constexpr int kMaxReach = 3;         // largest cell_div
 constexpr int kMaxRuns = (2 * kMaxReach + 1) * (2 * kMaxReach + 1);
 constexpr int kGridAxisMax = 1024;   // cells per binned axis (bounds the key rounding error)

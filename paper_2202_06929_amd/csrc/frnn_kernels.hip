@@ -532,8 +532,13 @@ __device__ __forceinline__ unsigned int wave_candidate_row(unsigned int m, int n
 
 // ------------------------------------------------------------------ search
 
+// Waves per SIMD the search asks the register allocator for: narrow rows fit in
+// 64 registers (8 waves); wider rows keep the compiler's choice (no spills).
 template <int DP>
-__global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sorted,
+constexpr int kSearchWaves = DP <= 8 ? 8 : 1;
+
+template <int DP>
+__global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float *__restrict__ sorted,
                                                    const unsigned int *__restrict__ sorted_id,
                                                    const unsigned int *__restrict__ sorted_key, unsigned int q_base,
                                                    unsigned int q_rem,
@@ -549,11 +554,15 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
     __shared__ unsigned int lst_all[kWaves][kQTile * kListCap];
     __shared__ unsigned int pre_all[kWaves][kQTile + 1];
     __shared__ unsigned int cnt_all[kWaves][kQTile];
+    __shared__ unsigned int qcnt_all[kWaves][kQTile];
+    __shared__ unsigned long long ring_all[kWaves][kRing];  // (q << 6 | lane) << 32 | bits of the partial sum
     __shared__ unsigned long long tested_w[kWaves];
     if (ctr->abort) return;
     unsigned int *lst = lst_all[wave_id()];
     unsigned int *tpre = pre_all[wave_id()];
     unsigned int *tcnt = cnt_all[wave_id()];
+    unsigned int *qcnt = qcnt_all[wave_id()];
+    unsigned long long *ring = ring_all[wave_id()];
     const int lane = lane_id();
     const unsigned int total_waves = gridDim.x * kWaves;
     constexpr int kLead = DP < 3 ? DP : 3;  // terms before the first exact rejection test
@@ -596,7 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
             const unsigned int M = wave_runs(cell - cell0, cell0, P, cell_start, start, pre);
             for (unsigned int q0 = qs; q0 < qe; q0 += kQTile) {
                 const int Qn = static_cast<int>(min(static_cast<unsigned int>(kQTile), qe - q0));
-                unsigned int cnt = 0;  // lane q holds the hit count of query q0 + q
+                if (lane < kQTile) qcnt[lane] = 0u;
                 // Candidate rows are fetched one chunk ahead so that their latency
                 // overlaps the tests of the current chunk.  Idle lanes read row 0 (any
                 // row is a valid address) and are masked out of every ballot.
@@ -618,14 +627,38 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
                     const unsigned int s = sn, jid = jn;
                     if (base + 64 < M) fetch(base + 64);
                     const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
+                    // Second stage for ring entries [h, h + nb): lane l finishes the sum of
+                    // entry h + l (candidate lane cl, query q) from the three-term partial
+                    // sum, in the same order as the first stage began it.
+                    auto finish = [&](unsigned int h, unsigned int nb) {
+                        wave_lds_sync();
+                        const bool act = static_cast<unsigned int>(lane) < nb;
+                        const unsigned int e = (h + lane) & (kRing - 1);
+                        const unsigned long long ent = act ? ring[e] : 0ull;
+                        const unsigned int code = static_cast<unsigned int>(ent >> 32);
+                        float acc = __uint_as_float(static_cast<unsigned int>(ent));
+                        const int cl = static_cast<int>(code & 63u);
+                        const unsigned int q = code >> 6;
+                        float cc[DP];
+#pragma unroll
+                        for (int k = kLead; k < DP; ++k) cc[k] = __shfl(c[k], cl);
+                        const unsigned int s2 = static_cast<unsigned int>(__shfl(static_cast<int>(s), cl));
+                        const unsigned int j2 = static_cast<unsigned int>(__shfl(static_cast<int>(jid), cl));
+                        acc = add_terms<kLead, DP, DP>(acc, cc, sorted + static_cast<size_t>(q0 + q) * DP);
+                        if (act && acc < r2 && s2 != q0 + q) {
+                            const unsigned int pos = atomicAdd(&qcnt[q], 1u);
+                            if (pos < static_cast<unsigned int>(kListCap)) lst[q * kListCap + pos] = j2;
+                        }
+                        wave_lds_sync();
+                    };
                     // Query rows are wave-uniform (scalar loads); the next one is
                     // requested before the current one is tested.
                     float qn[kPre];
 #pragma unroll
                     for (int k = 0; k < kPre; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
+                    unsigned int head = 0, tail = 0;
                     for (int q = 0; q < Qn; ++q) {
-                        const unsigned int qslot = q0 + q;
-                        const float *qrow = sorted + static_cast<size_t>(qslot) * DP;
+                        const float *qrow = sorted + static_cast<size_t>(q0 + q) * DP;
                         float qc[kPre];
 #pragma unroll
                         for (int k = 0; k < kPre; ++k) qc[k] = qn[k];
@@ -633,23 +666,26 @@ __global__ __launch_bounds__(kBlock) void k_search(const float *__restrict__ sor
 #pragma unroll
                             for (int k = 0; k < kPre; ++k) qn[k] = qrow[DP + k];
                         }
-                        float acc = add_terms_r<0, kLead, DP, kPre>(0.0f, c, qc);
+                        // First stage: three terms for all 64 candidates; pairs that are not
+                        // yet at r2 are queued (exact: the remaining terms only add).
+                        const float acc = add_terms_r<0, kLead, DP, kPre>(0.0f, c, qc);
                         const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2) & vmask;
                         if (m1 == 0ull) continue;
-                        acc = add_terms_r<kLead, kPre, DP, kPre>(acc, c, qc);
-                        acc = add_terms<kPre, DP, DP>(acc, c, qrow);
-                        const unsigned long long m2 = __builtin_amdgcn_ballot_w64(acc < r2) & vmask &
-                                                      ~__builtin_amdgcn_ballot_w64(s == qslot);
-                        if (m2 == 0ull) continue;
-                        const bool pass = (m2 >> lane) & 1ull;
-                        const unsigned int have = __builtin_amdgcn_readlane(cnt, q);
-                        if (pass) {
-                            const unsigned int pos = have + prefix_count(m2);
-                            if (pos < static_cast<unsigned int>(kListCap)) lst[q * kListCap + pos] = jid;
+                        if (valid && acc < r2) {
+                            const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
+                            ring[e] = (static_cast<unsigned long long>((static_cast<unsigned int>(q) << 6) |
+                                                                      static_cast<unsigned int>(lane)) << 32) |
+                                      __float_as_uint(acc);
                         }
-                        if (lane == q) cnt += static_cast<unsigned int>(__popcll(m2));
+                        tail += static_cast<unsigned int>(__popcll(m1));
+                        if (tail - head >= 64u) {
+                            finish(head, 64u);
+                            head += 64u;
+                        }
                     }
+                    if (tail != head) finish(head, tail - head);
                 }
+                const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
                 tested += static_cast<unsigned long long>(Qn) * M;
                 wave_lds_sync();
                 // Kept counts for every query; short lists are sorted by neighbour id and
