@@ -83,10 +83,9 @@ enum frnn_stage {
     FRNN_STAGE_CELLS = 2,    /* scan of the histogram */
     FRNN_STAGE_SCATTER = 3,  /* rows copied into cell order */
     FRNN_STAGE_SEARCH = 4,   /* neighbour-cell search */
-    FRNN_STAGE_LONG = 5,     /* long neighbour lists and the K cap */
-    FRNN_STAGE_OFFSETS = 6,  /* scan of kept counts */
-    FRNN_STAGE_PLACE = 7,    /* edges written in (i, j) order */
-    FRNN_STAGES = 8
+    FRNN_STAGE_LONG = 5,     /* kept totals, long neighbour lists and the K cap */
+    FRNN_STAGE_PLACE = 6,    /* output offsets; edges written in (i, j) order */
+    FRNN_STAGES = 7
 };
 
 /* Counts describing one call, for diagnostics and benchmarks. */

@@ -144,7 +144,7 @@ struct LaunchArgs {
     long long *src;
     long long *dst;
     hipStream_t stream;
-    hipEvent_t *events;     // 9 events bracketing the 8 stages, or null
+    hipEvent_t *events;     // 8 events bracketing the 7 stages, or null
     int search_blocks;      // resident workgroups of the search kernel
     int bounds_blocks;      // bounds partials per event (<= kBoundsBlocks)
     EventDesc ev0;          // event 0, written to ws.ev by the first kernel when ev_from_arg

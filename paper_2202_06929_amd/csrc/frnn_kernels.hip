@@ -1119,14 +1119,13 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
         default: launch_rows<64>(a, ws, vec4); break;
     }
     mark(6);
-    mark(7);
     hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
                        ws.rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n, ws.tpos,
                        ws.temp,
                        a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, ws.tested,
                        a.search_blocks, a.edge_off_out ? a.edge_off_out : ws.edge_off,
                        a.report_out ? a.report_out : ws.report);
-    mark(8);
+    mark(7);
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ MAX_D = 64
 MAX_K = 4096
 FLAG_TIMING = 1
 FLAG_EVENTS_RESIDENT = 2
-STAGES = ("bounds", "keys", "cells", "scatter", "search", "long", "offsets", "place")
+STAGES = ("bounds", "keys", "cells", "scatter", "search", "long", "place")
 
 
 class FrnnError(RuntimeError):
@@ -45,7 +45,7 @@ class FrnnStats(ctypes.Structure):
                 ("n_cells", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
                 ("dims", ctypes.c_int32 * 3), ("cell", ctypes.c_float * 3),
                 ("capped_queries", ctypes.c_int32), ("overflow_queries", ctypes.c_int32),
-                ("stage_ms", ctypes.c_float * 8)]
+                ("stage_ms", ctypes.c_float * 7)]
 
     def as_dict(self) -> dict:
         return {"n_edges": self.n_edges, "candidates": self.candidates, "n_cells": self.n_cells,
