@@ -932,7 +932,7 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                                                        const unsigned long long *__restrict__ sums_kept2,
                                                        int groups_kept, const unsigned long long *__restrict__ tpos,
                                                        const unsigned int *__restrict__ temp,
-                                                       unsigned long long heavy_cap,
+                                                       unsigned long long temp_len, unsigned long long heavy_cap,
                                                        long long *__restrict__ src, long long *__restrict__ dst,
                                                        unsigned long long cap, const Plan *__restrict__ plans,
                                                        const Counters *__restrict__ ctr,
@@ -1028,8 +1028,11 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
             const int r = owner[p];
             const unsigned int pos = w0 + p;
             const long long out = static_cast<long long>(pre) + pos;
+            const unsigned long long tix = tp[r] + (pos - o[r]);
             src[out] = i0 + r - base_row[r];
-            dst[out] = static_cast<long long>(temp[tp[r] + (pos - o[r])]) - base_row[r];
+            // The list positions come from the search; the bound only keeps a
+            // corrupted position from reading outside the workspace.
+            dst[out] = tix < temp_len ? static_cast<long long>(temp[tix]) - base_row[r] : -1ll;
         }
         __syncthreads();
     }
@@ -1121,7 +1124,7 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
     mark(6);
     hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
                        ws.rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n, ws.tpos,
-                       ws.temp,
+                       ws.temp, static_cast<unsigned long long>(ws.rows) * kListCap + a.edge_capacity,
                        a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, ws.tested,
                        a.search_blocks, a.edge_off_out ? a.edge_off_out : ws.edge_off,
                        a.report_out ? a.report_out : ws.report);
