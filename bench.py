@@ -147,7 +147,7 @@ def summarize(trace_dir: str, fetch_dir: str, write_dir: str, cfetch_dir: str, c
     def short(k):
         return k.replace("(anonymous namespace)::", "").replace("frnn::", "").replace("void ", "").split("(")[0]
 
-    rows = list(csv.DictReader(open(one(trace_dir, "*kernel_stats.csv"))))
+    rows = [r for r in csv.DictReader(open(one(trace_dir, "*kernel_stats.csv"))) if short(r["Name"]).startswith("k_")]
     out = ["# rocprofv3 summary: single event, 120,000 points, 8-D float32, r=0.1, K=256", "",
            f"kernel sources sha256/16: {kernel_source_digest()}", "", "## Kernel durations", "",
            f"command: `{commands[0]}`", "", "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
@@ -172,11 +172,12 @@ def summarize(trace_dir: str, fetch_dir: str, write_dir: str, cfetch_dir: str, c
             f"copy kernel `{ck}` of 256 MiB reads FETCH_SIZE {cf[ck]:.0f} KiB and WRITE_SIZE {cw[ck]:.0f} KiB "
             f"per dispatch: scale factors fetch x{f_scale:.3f}, write x{w_scale:.3f}", "",
             "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes |", "|---|---|---|---|"]
-    for k in fetch:
+    ours = [k for k in fetch if k.startswith("k_")]
+    for k in ours:
         b = int(round((fetch[k] * f_scale + write.get(k, 0.0) * w_scale) * 1024))
         out.append(f"| {k} | {fetch[k]:.1f} | {write.get(k, 0.0):.1f} | {b} |")
     lines = []
-    for k in fetch:
+    for k in ours:
         b = int(round((fetch[k] * f_scale + write.get(k, 0.0) * w_scale) * 1024))
         lines.append(f"traffic {k} bytes per launch: {b}")
     out += [""] + lines + [""]

@@ -195,7 +195,17 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
     a.src = reinterpret_cast<long long *>(src);
     a.dst = reinterpret_cast<long long *>(dst);
     a.stream = stream;
-    a.search_blocks = search_blocks_cached(a.dpad);
+    // One resident wave per SIMD slot when each gets few rows; with many rows per
+    // wave, up to four times as many workgroups as fit at once, so that the
+    // hardware hands the remaining shares to whichever workgroups finish first.
+    {
+        const int resident = search_blocks_cached(a.dpad);
+        const long long per_wave = rows / (static_cast<long long>(resident) * kWaves);
+        long long m = per_wave / 24;
+        m = m < 1 ? 1 : (m > 4 ? 4 : m);
+        const long long b = resident * m;
+        a.search_blocks = static_cast<int>(b > kMaxSearchBlocks ? kMaxSearchBlocks : b);
+    }
     // About 16 coordinates per thread of the bounds pass, at most kBoundsBlocks blocks per event.
     const long long bb = (static_cast<long long>(max_n) * d + 16 * kBlock - 1) / (16 * kBlock);
     a.bounds_blocks = static_cast<int>(bb < 1 ? 1 : (bb > kBoundsBlocks ? kBoundsBlocks : bb));
