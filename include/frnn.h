@@ -176,6 +176,51 @@ int frnn_build_events_async(const float *const *event_points, const int64_t *eve
                             int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *edge_offsets_device,
                             const frnn_config *config, void *stream);
 
+/* ---- Track labeling ------------------------------------------------------
+ * Weakly connected components of an edge list (paper, Section 2: the edges whose
+ * score passes a threshold are kept, and each weakly connected component is a
+ * track candidate; Section 3.2: the labeling uses the edge list that exists):
+ *
+ *   kept(e)   = scores == NULL or scores[e] > threshold (strict)
+ *   label[v]  = the smallest vertex id joined to v by a path of kept edges taken
+ *               in either direction (v itself when there is none)
+ *
+ * The labels are unique, so two correct implementations produce identical bytes.
+ * Self-loops and repeated edges are allowed.
+ */
+
+/* Bytes of device workspace for a graph of n_vertices vertices (0 for
+ * n_vertices < 0 or >= 2^31).  Host-only arithmetic. */
+size_t frnn_components_workspace_bytes(int64_t n_vertices);
+
+/* Labels the vertices of the graph.
+ *   src, dst      device, int64 [n_edges] each: edge e joins src[e] and dst[e]
+ *                 (for instance the output of frnn_build); every endpoint must lie in
+ *                 [0, n_vertices), else FRNN_ERR_ARG
+ *   n_edges       >= 0 (0: every vertex is its own component)
+ *   n_vertices    0 <= n_vertices < 2^31 (FRNN_ERR_UNSUPPORTED above)
+ *   scores        device, float32 [n_edges], or NULL to keep every edge
+ *   threshold     edges with scores[e] > threshold are kept
+ *   workspace     device scratch of at least frnn_components_workspace_bytes(n_vertices)
+ *                 bytes, 256-byte aligned; contents on entry do not matter
+ *   labels        device, int64 [n_vertices]: receives label[v]
+ *   n_components  host, may be NULL: receives the number of components
+ *   stream        hipStream_t as void*
+ * Blocks until the work enqueued on `stream` has finished.  FRNN_ERR_HIP also
+ * reports the (never expected) case of the hook loop reaching its internal bound. */
+int frnn_components(const int64_t *src, const int64_t *dst, int64_t n_edges, int64_t n_vertices,
+                    const float *scores, float threshold, void *workspace, size_t workspace_bytes,
+                    int64_t *labels, int64_t *n_components, void *stream);
+
+/* frnn_components without waiting: enqueues the work on `stream` and returns.
+ *   result_device  device, int64 [2]: receives the number of components, then a
+ *                  status word (FRNN_OK, FRNN_ERR_ARG for an endpoint out of range,
+ *                  FRNN_ERR_HIP for the internal bound)
+ * Only kernels are enqueued, so the call can be captured into a HIP graph. */
+int frnn_components_async(const int64_t *src, const int64_t *dst, int64_t n_edges, int64_t n_vertices,
+                          const float *scores, float threshold, void *workspace, size_t workspace_bytes,
+                          int64_t *labels, int64_t *result_device, void *stream);
+
 /* Static name of a status code. */
 const char *frnn_status_string(int status);
 

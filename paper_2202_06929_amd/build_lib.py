@@ -20,7 +20,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfrnn.so")
-SOURCES = [os.path.join(CSRC, "frnn_kernels.hip"), os.path.join(CSRC, "frnn_api.cpp")]
+SOURCES = [os.path.join(CSRC, "frnn_kernels.hip"), os.path.join(CSRC, "frnn_api.cpp"),
+           os.path.join(CSRC, "frnn_components.hip")]
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -42,7 +43,10 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     """Always recompiles libfrnn.so; returns its path."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-shared", "-x", "hip", SOURCES[0], "-x", "hip", SOURCES[1], "-o", tmp]
+    cmd = [hipcc(), *HIP_FLAGS, "-shared"]
+    for src in SOURCES:
+        cmd += ["-x", "hip", src]
+    cmd += ["-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)

@@ -1,0 +1,202 @@
+// Track labeling on the FRNN edge list: weakly connected components of the kept
+// edges, every vertex labeled with the smallest vertex id of its component
+// (paper, Section 2: the edges whose score passes a threshold are kept and each
+// weakly connected component is a track candidate; Section 3.2: the labeling
+// runs on the edge list that already exists).
+//
+// Lock-free union-find on a parent array (one 32-bit entry per vertex):
+//   k_cc_init   parent[v] = v
+//   k_cc_hook   one thread per kept edge: find both roots (path halving), hook
+//               the larger root under the smaller one with a compare-and-swap,
+//               retry from the new roots if another thread hooked it first
+//   k_cc_label  label[v] = root of v; counts the roots (components)
+// Parent pointers only ever point to smaller ids (hooks go from the larger root
+// to the smaller, halving jumps to an ancestor), so there are no cycles and every
+// find ends.  When all edges are done each component is one tree, and its root is
+// its smallest vertex: that vertex's parent cannot be smaller, so it is a root.
+// Loads and stores of the parent array are device-scope atomics, so a thread never
+// works from a stale copy held by another XCD's cache.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "frnn.h"
+
+namespace {
+
+constexpr int kCcBlock = 256;
+// Rounds of the hook loop per edge before the call reports an internal error.  A
+// round repeats only after another thread merged one of the two trees, so a
+// correct run needs at most one round per merge; the bound is a safety net.
+constexpr unsigned int kMaxHookRounds = 1u << 20;
+
+struct CcState {
+    unsigned int status;             // bit 0: endpoint out of range; bit 1: hook bound reached
+    unsigned int pad;
+    unsigned long long n_components;
+};
+
+__device__ __forceinline__ unsigned int ld(const unsigned int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st(unsigned int *p, unsigned int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x, halving the path on the way (x is pointed at its grandparent).
+__device__ unsigned int cc_find(unsigned int *parent, unsigned int x) {
+    for (;;) {
+        const unsigned int p = ld(parent + x);
+        if (p == x) return x;
+        const unsigned int gp = ld(parent + p);
+        if (gp == p) return p;
+        st(parent + x, gp);
+        x = gp;
+    }
+}
+
+__global__ __launch_bounds__(kCcBlock) void k_cc_init(unsigned int *parent, long long n, CcState *state) {
+    const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
+    for (long long v = static_cast<long long>(blockIdx.x) * kCcBlock + threadIdx.x; v < n; v += stride)
+        parent[v] = static_cast<unsigned int>(v);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        CcState z = {};
+        *state = z;
+    }
+}
+
+__global__ __launch_bounds__(kCcBlock) void k_cc_hook(const long long *__restrict__ src,
+                                                      const long long *__restrict__ dst, long long n_edges,
+                                                      long long n, const float *__restrict__ scores,
+                                                      float threshold, unsigned int *parent, CcState *state) {
+    const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
+    for (long long e = static_cast<long long>(blockIdx.x) * kCcBlock + threadIdx.x; e < n_edges; e += stride) {
+        if (scores && !(scores[e] > threshold)) continue;
+        const long long a = src[e], b = dst[e];
+        if (a < 0 || a >= n || b < 0 || b >= n) {
+            atomicOr(&state->status, 1u);
+            continue;
+        }
+        unsigned int u = static_cast<unsigned int>(a), v = static_cast<unsigned int>(b);
+        for (unsigned int round = 0;; ++round) {
+            u = cc_find(parent, u);
+            v = cc_find(parent, v);
+            if (u == v) break;
+            if (round >= kMaxHookRounds) {
+                atomicOr(&state->status, 2u);
+                break;
+            }
+            const unsigned int hi = u > v ? u : v, lo = u > v ? v : u;
+            unsigned int expected = hi;
+            if (__hip_atomic_compare_exchange_strong(parent + hi, &expected, lo, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kCcBlock) void k_cc_label(unsigned int *parent, long long n, long long *labels,
+                                                       CcState *state) {
+    __shared__ unsigned long long part[kCcBlock / 64];
+    const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
+    unsigned long long roots = 0;
+    for (long long v = static_cast<long long>(blockIdx.x) * kCcBlock + threadIdx.x; v < n; v += stride) {
+        const unsigned int r = cc_find(parent, static_cast<unsigned int>(v));
+        labels[v] = static_cast<long long>(r);
+        roots += r == static_cast<unsigned int>(v) ? 1ull : 0ull;
+    }
+    for (int o = 32; o > 0; o >>= 1) roots += __shfl_xor(roots, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = roots;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kCcBlock / 64; ++w) t += part[w];
+        if (t) atomicAdd(&state->n_components, t);
+    }
+}
+
+// Copies the state into the caller's device result [n_components, status].
+__global__ void k_cc_result(const CcState *state, long long *result) {
+    const unsigned int s = state->status;
+    result[0] = static_cast<long long>(state->n_components);
+    result[1] = (s & 1u) ? FRNN_ERR_ARG : ((s & 2u) ? FRNN_ERR_HIP : FRNN_OK);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+int grid_for(long long items) {
+    const long long b = (items + kCcBlock - 1) / kCcBlock;
+    return static_cast<int>(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+int check(const int64_t *src, const int64_t *dst, int64_t n_edges, int64_t n_vertices, void *workspace,
+          size_t workspace_bytes, int64_t *labels) {
+    if (n_edges < 0 || n_vertices < 0) return FRNN_ERR_ARG;
+    if (n_vertices >= (int64_t{1} << 31)) return FRNN_ERR_UNSUPPORTED;
+    if (n_edges > 0 && (!src || !dst)) return FRNN_ERR_ARG;
+    if (n_vertices > 0 && !labels) return FRNN_ERR_ARG;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
+    if (workspace_bytes < frnn_components_workspace_bytes(n_vertices)) return FRNN_ERR_WORKSPACE;
+    return FRNN_OK;
+}
+
+int enqueue(const int64_t *src, const int64_t *dst, int64_t n_edges, int64_t n_vertices, const float *scores,
+            float threshold, void *workspace, int64_t *labels, int64_t *result_device, hipStream_t s) {
+    CcState *state = static_cast<CcState *>(workspace);
+    unsigned int *parent = reinterpret_cast<unsigned int *>(static_cast<char *>(workspace) + 256);
+    const long long n = n_vertices;
+    hipLaunchKernelGGL(k_cc_init, dim3(grid_for(n)), dim3(kCcBlock), 0, s, parent, n, state);
+    if (n_edges > 0)
+        hipLaunchKernelGGL(k_cc_hook, dim3(grid_for(n_edges)), dim3(kCcBlock), 0, s,
+                           reinterpret_cast<const long long *>(src), reinterpret_cast<const long long *>(dst),
+                           static_cast<long long>(n_edges), n, scores, threshold, parent, state);
+    if (n > 0)
+        hipLaunchKernelGGL(k_cc_label, dim3(grid_for(n)), dim3(kCcBlock), 0, s, parent, n,
+                           reinterpret_cast<long long *>(labels), state);
+    hipLaunchKernelGGL(k_cc_result, dim3(1), dim3(1), 0, s, state, reinterpret_cast<long long *>(result_device));
+    return hipGetLastError() == hipSuccess ? FRNN_OK : FRNN_ERR_HIP;
+}
+
+thread_local long long *t_result = nullptr;  // pinned host copy of [n_components, status]
+
+}  // namespace
+
+extern "C" size_t frnn_components_workspace_bytes(int64_t n_vertices) {
+    if (n_vertices < 0 || n_vertices >= (int64_t{1} << 31)) return 0;
+    // state, a 16-byte device result, then the parent array
+    return 256 + align256(sizeof(unsigned int) * static_cast<size_t>(n_vertices)) + 256;
+}
+
+extern "C" int frnn_components_async(const int64_t *src, const int64_t *dst, int64_t n_edges, int64_t n_vertices,
+                                     const float *scores, float threshold, void *workspace, size_t workspace_bytes,
+                                     int64_t *labels, int64_t *result_device, void *stream) {
+    const int st = check(src, dst, n_edges, n_vertices, workspace, workspace_bytes, labels);
+    if (st != FRNN_OK) return st;
+    if (!result_device) return FRNN_ERR_ARG;
+    return enqueue(src, dst, n_edges, n_vertices, scores, threshold, workspace, labels, result_device,
+                   static_cast<hipStream_t>(stream));
+}
+
+extern "C" int frnn_components(const int64_t *src, const int64_t *dst, int64_t n_edges, int64_t n_vertices,
+                               const float *scores, float threshold, void *workspace, size_t workspace_bytes,
+                               int64_t *labels, int64_t *n_components, void *stream) {
+    const int st = check(src, dst, n_edges, n_vertices, workspace, workspace_bytes, labels);
+    if (st != FRNN_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!t_result) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 2 * sizeof(long long), hipHostMallocDefault) != hipSuccess) return FRNN_ERR_HIP;
+        t_result = static_cast<long long *>(p);
+    }
+    int64_t *result_device = reinterpret_cast<int64_t *>(
+        static_cast<char *>(workspace) + 256 + align256(sizeof(unsigned int) * static_cast<size_t>(n_vertices)));
+    const int e = enqueue(src, dst, n_edges, n_vertices, scores, threshold, workspace, labels, result_device, s);
+    if (e != FRNN_OK) return e;
+    if (hipMemcpyAsync(t_result, result_device, 2 * sizeof(long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return FRNN_ERR_HIP;
+    if (n_components) *n_components = t_result[0];
+    return static_cast<int>(t_result[1]);
+}

@@ -100,6 +100,12 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.frnn_build_events_async.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(i64), i32, i32,
                                             ctypes.c_float, i32, vp, ctypes.c_size_t, vp, vp, i64, vp,
                                             ctypes.POINTER(FrnnConfig), vp]
+    lib.frnn_components_workspace_bytes.restype = ctypes.c_size_t
+    lib.frnn_components_workspace_bytes.argtypes = [i64]
+    for name, last in (("frnn_components", ctypes.POINTER(ctypes.c_int64)), ("frnn_components_async", vp)):
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = [vp, vp, i64, i64, vp, ctypes.c_float, vp, ctypes.c_size_t, vp, last, vp]
     lib.frnn_status_string.restype = ctypes.c_char_p
     lib.frnn_status_string.argtypes = [ctypes.c_int]
     return lib
@@ -291,3 +297,53 @@ def build_events_async(event_points: list[torch.Tensor], r: float, K: int, works
         ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.c_void_p(src.data_ptr()),
         ctypes.c_void_p(dst.data_ptr()), src.numel(), ctypes.c_void_p(edge_offsets.data_ptr()),
         ctypes.byref(cfg) if cfg is not None else None, ctypes.c_void_p(_stream_handle(event_points[0].device)))
+
+
+def components_workspace_bytes(n_vertices: int) -> int:
+    return int(lib().frnn_components_workspace_bytes(n_vertices))
+
+
+def _edge_arrays(src: torch.Tensor, dst: torch.Tensor, scores: torch.Tensor | None):
+    for t in (src, dst):
+        if t.dtype != torch.int64 or t.dim() != 1 or not t.is_contiguous() or not t.is_cuda:
+            raise TypeError("src and dst must be contiguous 1-D int64 device tensors")
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in length")
+    if scores is not None and (scores.dtype != torch.float32 or scores.numel() != src.numel()
+                               or not scores.is_contiguous() or not scores.is_cuda):
+        raise TypeError("scores must be a contiguous float32 device tensor with one entry per edge")
+
+
+def components(src: torch.Tensor, dst: torch.Tensor, n_vertices: int, scores: torch.Tensor | None = None,
+               threshold: float = 0.0) -> tuple[torch.Tensor, int]:
+    """Track labels: (labels int64 [n_vertices], number of components).
+
+    Weakly connected components of the kept edges (all edges, or those with
+    scores > threshold), each vertex labeled with the smallest vertex id of its
+    component (frnn_components)."""
+    _edge_arrays(src, dst, scores)
+    dev = src.device
+    labels = torch.empty(max(n_vertices, 0), dtype=torch.int64, device=dev)
+    ws = torch.empty(max(components_workspace_bytes(n_vertices), 256), dtype=torch.uint8, device=dev)
+    nc = ctypes.c_int64(0)
+    st = lib().frnn_components(
+        ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(), n_vertices,
+        ctypes.c_void_p(scores.data_ptr()) if scores is not None else None, ctypes.c_float(threshold),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(labels.data_ptr()), ctypes.byref(nc),
+        ctypes.c_void_p(_stream_handle(dev)))
+    if st != FRNN_OK:
+        raise FrnnError(st, status_string(st))
+    return labels, int(nc.value)
+
+
+def components_async(src: torch.Tensor, dst: torch.Tensor, n_vertices: int, workspace: torch.Tensor,
+                     labels: torch.Tensor, result: torch.Tensor, scores: torch.Tensor | None = None,
+                     threshold: float = 0.0) -> int:
+    """Enqueues frnn_components_async on the current stream; result (device int64 [2])
+    receives the number of components and a status word."""
+    _edge_arrays(src, dst, scores)
+    return lib().frnn_components_async(
+        ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(), n_vertices,
+        ctypes.c_void_p(scores.data_ptr()) if scores is not None else None, ctypes.c_float(threshold),
+        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.c_void_p(labels.data_ptr()),
+        ctypes.c_void_p(result.data_ptr()), ctypes.c_void_p(_stream_handle(src.device)))

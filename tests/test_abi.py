@@ -155,3 +155,26 @@ def test_distance_kernels_use_no_fused_or_packed_float_ops(tmp_path):
         assert not bad, f"{name}: {sorted(set(bad))}"
         assert re.search(r"\bv_(sub|subrev)_f32", body) and re.search(r"\bv_mul_f32", body)
     assert checked >= 16
+
+
+def test_components_argument_errors_and_workspace_sizes(lib):
+    from paper_2202_06929_amd import frnn
+    ws = lib.frnn_components_workspace_bytes
+    assert ws(-1) == 0 and ws(2 ** 31) == 0
+    sizes = [ws(n) for n in (0, 1, 1000, 120_000, 2 ** 31 - 1)]
+    assert all(a <= b for a, b in zip(sizes, sizes[1:])) and sizes[0] > 0
+    fake = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: every check fails first
+
+    def call(src=fake, dst=fake, e=10, n=10, wsp=fake, wsb=1 << 30, labels=fake):
+        return lib.frnn_components(src, dst, e, n, None, ctypes.c_float(0.5), wsp, wsb, labels, None, None)
+
+    assert call(e=-1) == frnn.FRNN_ERR_ARG
+    assert call(n=-1) == frnn.FRNN_ERR_ARG
+    assert call(n=2 ** 31) == frnn.FRNN_ERR_UNSUPPORTED
+    assert call(src=None) == frnn.FRNN_ERR_ARG
+    assert call(labels=None) == frnn.FRNN_ERR_ARG
+    assert call(wsp=None) == frnn.FRNN_ERR_ARG
+    assert call(wsp=ctypes.c_void_p((1 << 20) + 8)) == frnn.FRNN_ERR_ARG  # not 256-byte aligned
+    assert call(wsb=ws(10) - 1) == frnn.FRNN_ERR_WORKSPACE
+    assert lib.frnn_components_async(fake, fake, 10, 10, None, ctypes.c_float(0.5), fake, 1 << 30, fake, None,
+                                     None) == frnn.FRNN_ERR_ARG  # no result buffer
