@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--cell-div", type=int, default=None)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-labeling", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run the counter calibration copy and exit")
     ap.add_argument("--summarize", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="print a markdown summary of rocprofv3 output folders and exit")
@@ -345,6 +346,63 @@ def served_bench(log, n_events: int = 300, load: float = 1.0) -> dict:
             "parity": "sampled served events identical to the same event alone"}
 
 
+def labeling_bench(spec, X, pts, steps: int, warmup: int, log, cpu: bool) -> dict:
+    """Track labeling (weakly connected components) of the event's FRNN graph.
+
+    Steps run back to back through frnn_components_async, each result slot checked
+    afterwards; one launch of each kernel is timed with HIP events on the stream.
+    The labels are compared with the CPU oracle's on the oracle's own edge list.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2202_06929_amd import frnn
+
+    dev = pts.device
+    edges = frnn.build(pts, spec.r, spec.K)
+    src, dst = edges[0].contiguous(), edges[1].contiguous()
+    n, E = spec.n, int(src.numel())
+    ws = torch.empty(frnn.components_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    lab = torch.empty(n, dtype=torch.int64, device=dev)
+    res = torch.full((warmup + steps, 2), -1, dtype=torch.int64, device=dev)
+    for w in range(warmup):
+        frnn.components_async(src, dst, n, ws, lab, res[w])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        frnn.components_async(src, dst, n, ws, lab, res[warmup + k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r = res.cpu().numpy()
+    if not ((r[:, 1] == 0).all() and (r[:, 0] == r[0, 0]).all()):
+        raise RuntimeError("a labeling step failed")
+    got = lab.cpu().numpy()
+    from oracle import components as cc_oracle
+    from oracle import oracle
+    g = oracle.frnn_grid(X, spec.r, spec.K)
+    want = cc_oracle.labels(g[0], g[1], n)
+    if not np.array_equal(got, want):
+        raise RuntimeError("labels differ from the oracle")
+    # Algorithmic bytes: both endpoint arrays read once (16 E), the parent array
+    # written, read back and the int64 labels written (4 n + 4 n + 8 n).
+    alg = 16 * E + 16 * n
+    per = wall / steps
+    out = {"workload": f"labels of the single event's FRNN graph: {n} vertices, {E} edges",
+           "events_per_s": steps / wall, "ms_per_event": per * 1e3, "components": int(r[0, 0]),
+           "hbm_gbs_algorithmic": alg / per / 1e9, "hbm_frac": alg / per / 1e9 / HBM_PEAK_GBS,
+           "alg_bytes": alg, "parity": "labels identical to the oracle's"}
+    if cpu:
+        runs = []
+        t = time.perf_counter()
+        while len(runs) < 3 or time.perf_counter() - t < 3.0:
+            a = time.perf_counter()
+            cc_oracle.labels(g[0], g[1], n)
+            runs.append(time.perf_counter() - a)
+        out["cpu_oracle_events_per_s"] = len(runs) / sum(runs)
+    log(f"labeling: {out['ms_per_event']:.3f} ms per event, {out['components']} components")
+    return out
+
+
 def main():
     args = parse()
     if args.summarize:
@@ -454,6 +512,8 @@ def main():
         "candidates": st["candidates"],
         "roofline": roofline, "roofline_hbm": roofline_hbm,
     }
+    if args.workload == "single" and not args.no_labeling:
+        result["labeling"] = labeling_bench(spec, X, pts, args.steps, args.warmup, log, not args.no_cpu_baseline)
     if not args.no_batched:
         result["batched"] = batched_bench(args.steps, args.warmup, log)
     if not args.no_served:

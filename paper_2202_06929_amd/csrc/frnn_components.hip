@@ -14,8 +14,13 @@
 // to the smaller, halving jumps to an ancestor), so there are no cycles and every
 // find ends.  When all edges are done each component is one tree, and its root is
 // its smallest vertex: that vertex's parent cannot be smaller, so it is a root.
-// Loads and stores of the parent array are device-scope atomics, so a thread never
-// works from a stale copy held by another XCD's cache.
+// Finds read the parent array with ordinary (cached) loads: a stale entry is still
+// an ancestor, because entries only ever move up the tree, so a find returns a
+// vertex of the right tree, perhaps not its current root.  Equal results therefore
+// prove two vertices share a tree.  Hooks are device-scope compare-and-swaps on
+// the presumed root; a failed one returns that vertex's current parent, a
+// strictly smaller id, and the hook resumes from there, so every retry makes
+// progress on fresh data.  Path-halving stores are device-scope atomic stores.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -37,9 +42,7 @@ struct CcState {
     unsigned long long n_components;
 };
 
-__device__ __forceinline__ unsigned int ld(const unsigned int *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ unsigned int ld(const unsigned int *p) { return *p; }
 
 __device__ __forceinline__ void st(unsigned int *p, unsigned int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -79,11 +82,10 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_hook(const long long *__restric
             atomicOr(&state->status, 1u);
             continue;
         }
-        unsigned int u = static_cast<unsigned int>(a), v = static_cast<unsigned int>(b);
-        for (unsigned int round = 0;; ++round) {
-            u = cc_find(parent, u);
-            v = cc_find(parent, v);
-            if (u == v) break;
+        if (a == b) continue;
+        unsigned int u = cc_find(parent, static_cast<unsigned int>(a));
+        unsigned int v = cc_find(parent, static_cast<unsigned int>(b));
+        for (unsigned int round = 0; u != v; ++round) {
             if (round >= kMaxHookRounds) {
                 atomicOr(&state->status, 2u);
                 break;
@@ -93,6 +95,9 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_hook(const long long *__restric
             if (__hip_atomic_compare_exchange_strong(parent + hi, &expected, lo, __ATOMIC_RELAXED,
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 break;
+            // hi was hooked meanwhile: continue from its current parent (< hi).
+            u = cc_find(parent, expected);
+            v = lo;
         }
     }
 }
