@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=["single", "high", "tiny"], default="single")
+    ap.add_argument("--workload", choices=["single", "high", "tiny", "knn"], default="single")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cell-div", type=int, default=None)
     ap.add_argument("--no-batched", action="store_true")
@@ -420,7 +420,7 @@ def main():
 
     from paper_2202_06929_amd import events, frnn
 
-    spec = {"single": events.SINGLE, "high": events.HIGH, "tiny": events.TINY}[args.workload]
+    spec = {"single": events.SINGLE, "high": events.HIGH, "tiny": events.TINY, "knn": events.KNN}[args.workload]
     X, _ = events.generate(spec)
     dev = torch.device("cuda:0")
     pts = torch.from_numpy(X).to(dev)

@@ -64,15 +64,16 @@ bool config_ok(const frnn_config *c, int d) {
 std::mutex g_blocks_mu;
 std::map<std::pair<int, int>, int> g_blocks;
 
-int search_blocks_cached(int dpad) {
+int search_blocks_cached(int dpad, bool sel) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const int key = dpad * 2 + (sel ? 1 : 0);
     std::lock_guard<std::mutex> lock(g_blocks_mu);
-    auto it = g_blocks.find({dev, dpad});
+    auto it = g_blocks.find({dev, key});
     if (it != g_blocks.end()) return it->second;
-    int b = search_blocks_for(dpad);
+    int b = search_blocks_for(dpad, sel);
     if (b > kMaxSearchBlocks) b = kMaxSearchBlocks;
-    g_blocks[{dev, dpad}] = b;
+    g_blocks[{dev, key}] = b;
     return b;
 }
 
@@ -130,6 +131,7 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.heavy = cv.take<HeavyEntry>(rows);
     ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap + static_cast<size_t>(edge_capacity));
     ws.tested = cv.take<unsigned long long>(kMaxSearchBlocks);
+    ws.capped_blk = cv.take<unsigned int>(kMaxSearchBlocks);
     ws.rows = rows;
     ws.cells = cells;
     ws.tiles_cells_n = static_cast<int>(tiles_cells);
@@ -199,7 +201,7 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
     // wave, up to four times as many workgroups as fit at once, so that the
     // hardware hands the remaining shares to whichever workgroups finish first.
     {
-        const int resident = search_blocks_cached(a.dpad);
+        const int resident = search_blocks_cached(a.dpad, K < kListCap);
         const long long per_wave = rows / (static_cast<long long>(resident) * kWaves);
         long long m = per_wave / 24;
         m = m < 1 ? 1 : (m > 4 ? 4 : m);

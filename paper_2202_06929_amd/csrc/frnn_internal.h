@@ -112,6 +112,7 @@ struct Workspace {
     HeavyEntry *heavy;          // [rows]
     unsigned int *temp;         // [rows * kListCap + edge_capacity] neighbour lists
     unsigned long long *tested; // [kMaxSearchBlocks] pairs examined per search workgroup
+    unsigned int *capped_blk;   // [kMaxSearchBlocks] capped queries per search workgroup
     long long rows;
     long long cells;
     int tiles_cells_n;
@@ -157,7 +158,8 @@ struct LaunchArgs {
 // per-event edge ranges in ws.edge_off.
 hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws);
 
-// Resident workgroups of the search kernel for rows padded to dpad (current device).
-int search_blocks_for(int dpad);
+// Resident workgroups of the search kernel for rows padded to dpad (current device);
+// sel: the variant for K below the list size.
+int search_blocks_for(int dpad, bool sel);
 
 }  // namespace frnn

@@ -537,7 +537,9 @@ __device__ __forceinline__ unsigned int wave_candidate_row(unsigned int m, int n
 template <int DP>
 constexpr int kSearchWaves = DP <= 8 ? 8 : 1;
 
-template <int DP>
+// SEL: the cap K is below kListCap, so a list that fits may still need the K
+// nearest of its hits: the lists then also hold each hit's distance.
+template <int DP, bool SEL>
 __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float *__restrict__ sorted,
                                                    const unsigned int *__restrict__ sorted_id,
                                                    const unsigned int *__restrict__ sorted_key, unsigned int q_base,
@@ -550,15 +552,22 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                                    unsigned int *__restrict__ temp,
                                                    HeavyEntry *__restrict__ heavy,
                                                    Counters *__restrict__ ctr,
-                                                   unsigned long long *__restrict__ tested_out) {
+                                                   unsigned long long *__restrict__ tested_out,
+                                                   unsigned int *__restrict__ capped_out) {
     __shared__ unsigned int lst_all[kWaves][kQTile * kListCap];
+    __shared__ unsigned int lstd_all[SEL ? kWaves : 1][SEL ? kQTile * kListCap : 1];  // D bits of each hit
+    __shared__ unsigned long long thr_all[SEL ? kWaves : 1][SEL ? kQTile : 1];       // K-th smallest (D, j) key
     __shared__ unsigned int pre_all[kWaves][kQTile + 1];
     __shared__ unsigned int cnt_all[kWaves][kQTile];
     __shared__ unsigned int qcnt_all[kWaves][kQTile];
     __shared__ unsigned long long ring_all[kWaves][kRing];  // (q << 6 | lane) << 32 | bits of the partial sum
     __shared__ unsigned long long tested_w[kWaves];
+    __shared__ unsigned int capped_w[kWaves];
     if (ctr->abort) return;
     unsigned int *lst = lst_all[wave_id()];
+    unsigned int *lstd = lstd_all[SEL ? wave_id() : 0];
+    unsigned long long *thr = thr_all[SEL ? wave_id() : 0];
+    unsigned int capped = 0;
     unsigned int *tpre = pre_all[wave_id()];
     unsigned int *tcnt = cnt_all[wave_id()];
     unsigned int *qcnt = qcnt_all[wave_id()];
@@ -647,7 +656,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         acc = add_terms<kLead, DP, DP>(acc, cc, sorted + static_cast<size_t>(q0 + q) * DP);
                         if (act && acc < r2 && s2 != q0 + q) {
                             const unsigned int pos = atomicAdd(&qcnt[q], 1u);
-                            if (pos < static_cast<unsigned int>(kListCap)) lst[q * kListCap + pos] = j2;
+                            if (pos < static_cast<unsigned int>(kListCap)) {
+                                lst[q * kListCap + pos] = j2;
+                                if (SEL) lstd[q * kListCap + pos] = __float_as_uint(acc);
+                            }
                         }
                         wave_lds_sync();
                     };
@@ -688,14 +700,18 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
                 tested += static_cast<unsigned long long>(Qn) * M;
                 wave_lds_sync();
-                // Kept counts for every query; short lists are sorted by neighbour id and
-                // stored at a fixed place (kListCap slots per sorted row); longer ones and
-                // capped ones go to the long-list kernel.
+                // Kept counts for every query; lists that fit are sorted by neighbour id
+                // (after the K nearest are chosen, when the cap binds) and stored at a
+                // fixed place (kListCap slots per sorted row); longer ones go to the
+                // long-list kernel.
+                const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
+                                  (SEL || cnt <= static_cast<unsigned int>(K));
                 if (lane < Qn) {
                     const unsigned int slot = q0 + lane;
                     const unsigned int i = sorted_id[slot];
                     kept[i] = min(cnt, static_cast<unsigned int>(K));
-                    if (cnt <= static_cast<unsigned int>(kListCap) && cnt <= static_cast<unsigned int>(K)) {
+                    if (cnt > static_cast<unsigned int>(K)) ++capped;
+                    if (fits) {
                         tpos[i] = static_cast<unsigned long long>(slot) * kListCap;
                     } else {
                         const unsigned int h = atomicAdd(&ctr->heavy_count, 1u);
@@ -705,16 +721,15 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         he.cell = cell;
                         he.event = static_cast<unsigned int>(ev_cur);
                         heavy[h] = he;
-                        if (cnt > static_cast<unsigned int>(K)) atomicAdd(&ctr->capped, 1u);
                     }
                 }
-                // Sort the short lists together: the entries of all lists of the tile are
-                // numbered through a prefix over list lengths; each lane takes one entry,
-                // finds its query by binary search and its rank by counting the smaller
-                // entries of the same list.
+                // Sort the lists that fit together: the entries of all lists of the tile
+                // are numbered through a prefix over list lengths; each lane takes one
+                // entry, finds its query by binary search and its rank by counting the
+                // smaller entries of the same list.  With the cap binding, a first pass
+                // finds each list's K-th smallest (D, j) key (D >= 0, so its bits order
+                // like the value) and the entries above it are dropped.
                 {
-                    const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
-                                      cnt <= static_cast<unsigned int>(K);
                     const unsigned int take = fits ? cnt : 0u;
                     const unsigned int inc = wave_inclusive_scan(take);
                     const unsigned int T = __builtin_amdgcn_readlane(inc, 63);
@@ -723,21 +738,59 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         tcnt[lane] = take;
                     }
                     wave_lds_sync();
+                    auto entry_query = [&](unsigned int t) {
+                        int lo = 0, hi = Qn - 1;  // last query whose list starts at or before t
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (tpre[mid] <= t) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        return lo;
+                    };
+                    const unsigned int Ku = static_cast<unsigned int>(K);
+                    if (SEL) {
+                        for (unsigned int t0 = 0; t0 < T; t0 += 64) {
+                            const unsigned int t = t0 + lane;
+                            if (t < T) {
+                                const int lo = entry_query(t);
+                                const unsigned int cq = tcnt[lo];
+                                if (cq > Ku) {
+                                    const unsigned int *l = lst + lo * kListCap;
+                                    const unsigned int *ld = lstd + lo * kListCap;
+                                    const unsigned int x = t - tpre[lo];
+                                    const unsigned long long key =
+                                        (static_cast<unsigned long long>(ld[x]) << 32) | l[x];
+                                    unsigned int sr = 0;
+                                    for (unsigned int u = 0; u < cq; ++u)
+                                        sr += ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) < key ? 1u : 0u;
+                                    if (sr == Ku - 1u) thr[lo] = key;
+                                }
+                            }
+                        }
+                        wave_lds_sync();
+                    }
                     for (unsigned int t0 = 0; t0 < T; t0 += 64) {
                         const unsigned int t = t0 + lane;
                         if (t < T) {
-                            int lo = 0, hi = Qn - 1;  // last query whose list starts at or before t
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (tpre[mid] <= t) lo = mid;
-                                else hi = mid - 1;
-                            }
+                            const int lo = entry_query(t);
                             const unsigned int cq = tcnt[lo];
                             const unsigned int *l = lst + lo * kListCap;
-                            const unsigned int j = l[t - tpre[lo]];
+                            const unsigned int x = t - tpre[lo];
+                            const unsigned int j = l[x];
                             unsigned int rk = 0;
-                            for (unsigned int u = 0; u < cq; ++u) rk += l[u] < j ? 1u : 0u;
-                            temp[static_cast<size_t>(q0 + lo) * kListCap + rk] = j;
+                            if (SEL && cq > Ku) {
+                                const unsigned int *ld = lstd + lo * kListCap;
+                                const unsigned long long lim = thr[lo];
+                                if (((static_cast<unsigned long long>(ld[x]) << 32) | j) <= lim) {
+                                    for (unsigned int u = 0; u < cq; ++u)
+                                        rk += (l[u] < j && ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) <= lim)
+                                                  ? 1u : 0u;
+                                    temp[static_cast<size_t>(q0 + lo) * kListCap + rk] = j;
+                                }
+                            } else {
+                                for (unsigned int u = 0; u < cq; ++u) rk += l[u] < j ? 1u : 0u;
+                                temp[static_cast<size_t>(q0 + lo) * kListCap + rk] = j;
+                            }
                         }
                     }
                 }
@@ -745,12 +798,21 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
             }
         }
     }
-    if (lane == 0) tested_w[wave_id()] = tested;
+    capped = wave_sum(capped);
+    if (lane == 0) {
+        tested_w[wave_id()] = tested;
+        capped_w[wave_id()] = capped;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
-        for (int w = 0; w < kWaves; ++w) t += tested_w[w];
+        unsigned int c = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            t += tested_w[w];
+            c += capped_w[w];
+        }
         tested_out[blockIdx.x] = t;
+        capped_out[blockIdx.x] = c;
     }
 }
 
@@ -937,6 +999,7 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                                                        unsigned long long cap, const Plan *__restrict__ plans,
                                                        const Counters *__restrict__ ctr,
                                                        const unsigned long long *__restrict__ tested,
+                                                       const unsigned int *__restrict__ capped_blk,
                                                        int search_blocks, long long *__restrict__ edge_off,
                                                        Report *__restrict__ report) {
     static_assert(kPlaceBlock == kPlaceTile && kPlaceTile <= 256, "one query per thread, owner ids fit a byte");
@@ -963,17 +1026,21 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     const long long E = static_cast<long long>(tot);
     const bool overflow = static_cast<unsigned long long>(E) > cap || ctr->heavy_top > heavy_cap;
     if (b == 0) {
-        unsigned long long t = 0;
+        unsigned long long t = 0, cp = 0;
         if (!abort)
-            for (int k = threadIdx.x; k < search_blocks; k += kPlaceBlock) t += tested[k];
+            for (int k = threadIdx.x; k < search_blocks; k += kPlaceBlock) {
+                t += tested[k];
+                cp += capped_blk[k];
+            }
         t = block_sum(t, scratch);
+        cp = block_sum(cp, scratch);
         if (threadIdx.x == 0) {
             const Plan P = plans[0];
             Report rep;
             rep.n_edges = E;
             rep.tested = t;
             rep.abort = abort ? 1 : 0;
-            rep.capped = ctr->capped;
+            rep.capped = static_cast<unsigned int>(cp);
             rep.heavy = ctr->heavy_count;
             rep.n_cells = P.n_cells;
             for (int p = 0; p < 3; ++p) {
@@ -1050,11 +1117,16 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, ws.key,
                        ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id, ws.sorted_key);
     mark(4);
-    hipLaunchKernelGGL(k_search<DP>, dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
-                       ws.sorted_key, static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves)),
-                       static_cast<unsigned int>(rows % (static_cast<long long>(a.search_blocks) * kWaves)), ws.ev,
-                       a.n_events, ws.cell_start, ws.plans, a.r2, a.K,
-                       ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested);
+    const unsigned int sq_base = static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves));
+    const unsigned int sq_rem = static_cast<unsigned int>(rows % (static_cast<long long>(a.search_blocks) * kWaves));
+    if (a.K < kListCap)
+        hipLaunchKernelGGL((k_search<DP, true>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
+                           ws.sorted_id, ws.sorted_key, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
+                           a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk);
+    else
+        hipLaunchKernelGGL((k_search<DP, false>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
+                           ws.sorted_id, ws.sorted_key, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
+                           a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk);
     mark(5);
     const unsigned long long heavy_base = static_cast<unsigned long long>(rows) * kListCap;
     const long long hb = (static_cast<long long>(ws.tiles_kept_n) + kWaves - 1) / kWaves;
@@ -1066,9 +1138,11 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
 }
 
 template <int DP>
-int occupancy_blocks() {
+int occupancy_blocks(bool sel) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search<DP>, kBlock, 0) != hipSuccess || per_cu < 1)
+    const hipError_t e = sel ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search<DP, true>, kBlock, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search<DP, false>, kBlock, 0);
+    if (e != hipSuccess || per_cu < 1)
         per_cu = 1;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1079,16 +1153,16 @@ int occupancy_blocks() {
 
 }  // namespace
 
-int search_blocks_for(int dpad) {
+int search_blocks_for(int dpad, bool sel) {
     switch (dpad) {
-        case 4: return occupancy_blocks<4>();
-        case 8: return occupancy_blocks<8>();
-        case 12: return occupancy_blocks<12>();
-        case 16: return occupancy_blocks<16>();
-        case 24: return occupancy_blocks<24>();
-        case 32: return occupancy_blocks<32>();
-        case 48: return occupancy_blocks<48>();
-        default: return occupancy_blocks<64>();
+        case 4: return occupancy_blocks<4>(sel);
+        case 8: return occupancy_blocks<8>(sel);
+        case 12: return occupancy_blocks<12>(sel);
+        case 16: return occupancy_blocks<16>(sel);
+        case 24: return occupancy_blocks<24>(sel);
+        case 32: return occupancy_blocks<32>(sel);
+        case 48: return occupancy_blocks<48>(sel);
+        default: return occupancy_blocks<64>(sel);
     }
 }
 
@@ -1125,7 +1199,7 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
     hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
                        ws.rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n, ws.tpos,
                        ws.temp, static_cast<unsigned long long>(ws.rows) * kListCap + a.edge_capacity,
-                       a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, ws.tested,
+                       a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, ws.tested, ws.capped_blk,
                        a.search_blocks, a.edge_off_out ? a.edge_off_out : ws.edge_off,
                        a.report_out ? a.report_out : ws.report);
     mark(7);

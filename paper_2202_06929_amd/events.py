@@ -56,6 +56,10 @@ SINGLE = EventSpec(n=120_000, d=8, n_clusters=10_000, size_lo=5, size_hi=18, sig
                    noise_frac=0.15, r=0.1, K=256, seed=2)
 HIGH = EventSpec(n=300_000, d=12, n_clusters=22_000, size_lo=6, size_hi=20, sigma=0.03,
                  noise_frac=0.20, r=0.12, K=512, seed=3)
+# Nearest K, then the radius cut (the k-nearest-neighbour semantics of Section
+# 3.1): the single event's points with K = 8, which binds for about half the
+# queries (clusters of up to 18 points).
+KNN = dataclasses.replace(SINGLE, K=8)
 
 
 def batched_spec(n: int, seed: int) -> EventSpec:

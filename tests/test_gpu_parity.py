@@ -259,3 +259,30 @@ def test_served_requests_match_oracle():
     assert stats.completed == len(reqs)
     for req, X in zip(reqs, host):
         assert_same(np.ascontiguousarray(req.edges.cpu().numpy()), oracle.frnn_grid(X, spec.r, spec.K))
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 8, 15, 16])
+def test_small_caps_keep_the_nearest(K):
+    """Caps below the list size: the search picks the K nearest by (D, j) itself."""
+    spec = events.TINY
+    X, _ = events.generate(spec)
+    log(f"small cap K={K} on the tiny event")
+    assert_same(gpu_edges(X, spec.r, K), oracle.frnn_grid(X, spec.r, K))
+
+
+def test_nearest_eight_on_the_single_event():
+    """The kNN-then-radius workload: K = 8 binds for about half the queries."""
+    spec = events.KNN
+    X, _ = events.generate(spec)
+    log(f"knn workload n={spec.n} K={spec.K}")
+    pts = torch.from_numpy(X).to(DEV)
+    stats = frnn.FrnnStats()
+    cap = 16 * spec.n
+    ws = torch.empty(frnn.workspace_bytes(spec.n, spec.d, cap), dtype=torch.uint8, device=DEV)
+    out = torch.empty((2, cap), dtype=torch.int64, device=DEV)
+    st, E = frnn.build_into(pts, spec.r, spec.K, ws, out[0], out[1], None, stats)
+    assert st == frnn.FRNN_OK
+    want = oracle.frnn_grid(X, spec.r, spec.K)
+    assert_same(out[:, :E].cpu().numpy(), want)
+    assert stats.capped_queries == int((np.bincount(oracle.frnn_grid(X, spec.r, 4096)[0], minlength=spec.n)
+                                        > spec.K).sum())
