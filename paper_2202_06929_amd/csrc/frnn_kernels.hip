@@ -515,21 +515,6 @@ __device__ __forceinline__ unsigned int wave_runs(unsigned int cell, unsigned in
     return uniform(static_cast<unsigned int>(__shfl(inc, 63)));
 }
 
-// Maps candidate number m (per lane) to its sorted row: run r is the last run
-// whose `pre` is <= m; empty runs are skipped because the next run has the same
-// pre.  Call with the whole wave active.
-__device__ __forceinline__ unsigned int wave_candidate_row(unsigned int m, int nruns, unsigned int start,
-                                                           unsigned int pre) {
-    int r = 0;
-    for (int t = 1; t < nruns; ++t) {
-        const unsigned int p = __builtin_amdgcn_readlane(pre, t);  // t is wave-uniform
-        r += (m >= p) ? 1 : 0;
-    }
-    const unsigned int s0 = static_cast<unsigned int>(__shfl(start, r));
-    const unsigned int p0 = static_cast<unsigned int>(__shfl(pre, r));
-    return s0 + (m - p0);
-}
-
 // ------------------------------------------------------------------ search
 
 // Waves per SIMD the search asks the register allocator for: narrow rows fit in
@@ -620,9 +605,22 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 // row is a valid address) and are masked out of every ballot.
                 float cn[DP];
                 unsigned int sn, jn;
+                // rc: the run holding candidate b (wave-uniform).  Runs are consecutive
+                // ranges of candidates, so only the runs that start inside the chunk
+                // need to be compared with each lane's candidate number.
+                int rc = 0;
                 auto fetch = [&](unsigned int b) {
+                    while (rc + 1 < nruns && __builtin_amdgcn_readlane(pre, rc + 1) <= b) ++rc;
                     const unsigned int mm = b + lane;
-                    const unsigned int srow = wave_candidate_row(mm < M ? mm : 0u, nruns, start, pre);
+                    const unsigned int m = mm < M ? mm : b;
+                    int r = rc;
+                    for (int t = rc + 1; t < nruns; ++t) {
+                        const unsigned int p = __builtin_amdgcn_readlane(pre, t);
+                        if (p >= b + 64u) break;
+                        r += m >= p ? 1 : 0;
+                    }
+                    const unsigned int srow = static_cast<unsigned int>(__shfl(start, r)) +
+                                              (m - static_cast<unsigned int>(__shfl(pre, r)));
                     sn = mm < M ? srow : 0u;
                     load_row<DP>(sorted, sn, cn);
                     jn = sorted_id[sn];
