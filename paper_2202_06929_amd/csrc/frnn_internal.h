@@ -24,6 +24,7 @@ constexpr int kKeysBlock = 1024;     // threads per workgroup of the key/histogr
 constexpr int kPlaceBlock = 256;     // threads per workgroup of the placement pass
 constexpr int kPlaceTile = 256;      // queries per workgroup of the placement pass (and kept tile)
 constexpr int kKeptGroup = 64;       // kept tiles per second-level total
+constexpr int kFlatTiles = 4096;     // up to this many kept tiles, placement sums the tile totals directly
 constexpr int kOwnerWindow = 4096;   // output positions mapped to their query at a time in placement
 constexpr int kMaxEvents = 65535;  // events per call (the second grid dimension)
 

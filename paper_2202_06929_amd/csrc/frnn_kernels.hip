@@ -265,13 +265,22 @@ __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, 
     float mn[3] = {INFINITY, INFINITY, INFINITY};
     float mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     int bad = 0;
-    for (int b = lane_id(); b < nparts; b += 64) {
-        const BoundsPartial pb = part[b];
+    // Every lane loads its (at most kBoundsBlocks / 64) partials before folding them.
+    constexpr int kPartsPerLane = kBoundsBlocks / 64;
+    BoundsPartial pb[kPartsPerLane];
+#pragma unroll
+    for (int u = 0; u < kPartsPerLane; ++u) {
+        const int b = lane_id() + 64 * u;
+        if (b < nparts) pb[u] = part[b];
+    }
+#pragma unroll
+    for (int u = 0; u < kPartsPerLane; ++u) {
+        if (lane_id() + 64 * u >= nparts) continue;
         for (int p = 0; p < 3; ++p) {
-            mn[p] = fminf(mn[p], pb.mn[p]);
-            mx[p] = fmaxf(mx[p], pb.mx[p]);
+            mn[p] = fminf(mn[p], pb[u].mn[p]);
+            mx[p] = fmaxf(mx[p], pb[u].mx[p]);
         }
-        bad |= pb.nonfinite;
+        bad |= pb[u].nonfinite;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -859,7 +868,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
             s = wave_sum(s);
             if (lane_id() == 0) {
                 sums_kept[t] = s;
-                if (s) atomicAdd(&sums_kept2[t / kKeptGroup], s);
+                if (s && tiles_kept > kFlatTiles) atomicAdd(&sums_kept2[t / kKeptGroup], s);
             }
         }
     }
@@ -990,7 +999,8 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                                                        int n_events, const unsigned int *__restrict__ kept,
                                                        const unsigned long long *__restrict__ sums_kept,
                                                        const unsigned long long *__restrict__ sums_kept2,
-                                                       int groups_kept, const unsigned long long *__restrict__ tpos,
+                                                       int groups_kept, int tiles_kept,
+                                                       const unsigned long long *__restrict__ tpos,
                                                        const unsigned int *__restrict__ temp,
                                                        unsigned long long temp_len, unsigned long long heavy_cap,
                                                        long long *__restrict__ src, long long *__restrict__ dst,
@@ -1010,7 +1020,14 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     const int b = static_cast<int>(blockIdx.x);
     const int g = b / kKeptGroup;
     unsigned long long pre = 0, tot = 0;
-    if (!abort) {
+    if (!abort && tiles_kept <= kFlatTiles) {
+        // Few tiles: the tile totals are summed directly.
+        for (int t = threadIdx.x; t < tiles_kept; t += kPlaceBlock) {
+            const unsigned long long v = sums_kept[t];
+            tot += v;
+            if (t < b) pre += v;
+        }
+    } else if (!abort) {
         for (int t = threadIdx.x; t < groups_kept; t += kPlaceBlock) {
             const unsigned long long v = sums_kept2[t];
             tot += v;
@@ -1195,7 +1212,8 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
     }
     mark(6);
     hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
-                       ws.rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n, ws.tpos,
+                       ws.rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n,
+                       ws.tiles_kept_n, ws.tpos,
                        ws.temp, static_cast<unsigned long long>(ws.rows) * kListCap + a.edge_capacity,
                        a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, ws.tested, ws.capped_blk,
                        a.search_blocks, a.edge_off_out ? a.edge_off_out : ws.edge_off,

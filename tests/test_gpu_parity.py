@@ -286,3 +286,21 @@ def test_nearest_eight_on_the_single_event():
     assert_same(out[:, :E].cpu().numpy(), want)
     assert stats.capped_queries == int((np.bincount(oracle.frnn_grid(X, spec.r, 4096)[0], minlength=spec.n)
                                         > spec.K).sum())
+
+
+def test_large_batch_uses_grouped_offsets():
+    """More than 4096 placement tiles (over a million rows): output offsets come from
+    the two-level totals; every event equals the event built alone."""
+    sizes = [120_000] * 9
+    evs = [events.generate(events.batched_spec(n, 500 + k))[0] for k, n in enumerate(sizes)]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    assert (offsets[-1] + 255) // 256 > 4096
+    pts = torch.from_numpy(np.concatenate(evs)).to(DEV)
+    log(f"large batch: {offsets[-1]} rows")
+    edges, eo = frnn.build_batch(pts, offsets, 0.1, 256)
+    edges = edges.cpu().numpy()
+    for e, X in enumerate(evs):
+        got = np.ascontiguousarray(edges[:, eo[e]:eo[e + 1]])
+        assert_same(got, gpu_edges(X, 0.1, 256))
+        if e in (0, 8):
+            assert_same(got, oracle.frnn_grid(X, 0.1, 256))
