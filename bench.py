@@ -483,7 +483,7 @@ def main():
     ops = st["candidates"] * (3 * d + 1)
     roofline = {"bound": "alu", "achieved": ops / t_search / 1e12, "peak": VALU_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": ops / t_search / 1e12 / VALU_PEAK_TOPS,
-                "traffic": stored_traffic("k_search<8>") if dpad == 8 else None,
+                "traffic": stored_traffic("k_search<8, false>") if dpad == 8 and spec.K >= 16 else None,
                 "kernel": "k_search", "kernel_us": t_search * 1e6,
                 "work": f"{st['candidates']} candidate pairs x (3d+1) FP32 ops",
                 "timing": "HIP events on the call's stream around the search kernel, averaged over a second "
