@@ -246,7 +246,7 @@ def batched_bench(steps: int, warmup: int, log) -> dict:
     t_batch = (time.perf_counter() - t) / reps
 
     eo_dev = torch.zeros(len(sizes) + 2, dtype=torch.int64, device=dev)
-    rcfg = frnn.Config(dims=cfg.dims, cell_div=cfg.cell_div, events_resident=True)
+    rcfg = frnn.Config(dims=cfg.dims, cell_div=cfg.cell_div, grid_mult=cfg.grid_mult, events_resident=True)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -277,7 +277,8 @@ def batched_bench(steps: int, warmup: int, log) -> dict:
     n_ev = len(sizes)
     return {"workload": f"batched: {n_ev} events, hits uniform in [20000, 150000] (total {int(offsets[-1])}), "
                         "8-D float32, r=0.1, K=256",
-            "config": {"dims": list(cfg.dims) if cfg.dims else None, "cell_div": cfg.cell_div},
+            "config": {"dims": list(cfg.dims) if cfg.dims else None, "cell_div": cfg.cell_div,
+                       "grid_mult": cfg.grid_mult},
             "events_per_s_plain_loop": n_ev / t_plain, "events_per_s_batched_call": n_ev / t_batch,
             "events_per_s_graph": n_ev / t_graph, "ms_per_batch_graph": t_graph * 1e3,
             "edges_per_s_graph": total_e / t_graph, "edges": total_e,

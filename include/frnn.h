@@ -63,7 +63,9 @@ typedef struct frnn_config {
                           so the leading coordinates of the distance sum are unbinned. */
     int32_t cell_div;  /* cell edge = r * (1 + 2^-10) / cell_div, cell_div in {1, 2, 3}
                           (0 means 1).  Neighbours are searched cell_div cells away. */
-    int32_t tile;      /* query tile of the search kernel: 0 (default), 32 or 64 */
+    int32_t grid_mult; /* search workgroups as a multiple of those that fit on the GPU at
+                          once: 1, 2, 4 or 8; 0 (default) chooses from the rows per wave
+                          (1 for few rows, up to 4 for many) */
     int32_t flags;     /* FRNN_FLAG_* bits */
 } frnn_config;
 

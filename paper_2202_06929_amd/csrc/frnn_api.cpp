@@ -55,7 +55,8 @@ bool config_ok(const frnn_config *c, int d) {
         if (c->dims[0] == c->dims[2] || c->dims[1] == c->dims[2]) return false;
     }
     if (c->cell_div < 0 || c->cell_div > kMaxReach) return false;
-    if (c->tile != 0 && c->tile != 32 && c->tile != 64) return false;
+    if (c->grid_mult != 0 && c->grid_mult != 1 && c->grid_mult != 2 && c->grid_mult != 4 && c->grid_mult != 8)
+        return false;
     if (c->flags & ~(FRNN_FLAG_TIMING | FRNN_FLAG_EVENTS_RESIDENT)) return false;
     return true;
 }
@@ -205,6 +206,7 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
         const long long per_wave = rows / (static_cast<long long>(resident) * kWaves);
         long long m = per_wave / 24;
         m = m < 1 ? 1 : (m > 4 ? 4 : m);
+        if (config && config->grid_mult > 0) m = config->grid_mult;
         const long long b = resident * m;
         a.search_blocks = static_cast<int>(b > kMaxSearchBlocks ? kMaxSearchBlocks : b);
     }

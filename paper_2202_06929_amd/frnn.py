@@ -37,7 +37,7 @@ class FrnnError(RuntimeError):
 
 class FrnnConfig(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int32 * 3), ("cell_div", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("grid_mult", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class FrnnStats(ctypes.Structure):
@@ -60,7 +60,7 @@ class Config:
 
     dims: tuple[int, int, int] | None = None  # binned coordinates (default: the last three)
     cell_div: int = 1                           # cell edge = r (1 + 2^-10) / cell_div
-    tile: int = 0
+    grid_mult: int = 0                          # search workgroups per resident slot (0: automatic)
     timing: bool = False                        # per-stage HIP event timing in the stats
     events_resident: bool = False               # batch event table already in the workspace
 
@@ -70,7 +70,7 @@ class Config:
             for p in range(3):
                 c.dims[p] = int(self.dims[p])
         c.cell_div = int(self.cell_div)
-        c.tile = int(self.tile)
+        c.grid_mult = int(self.grid_mult)
         c.flags = (FLAG_TIMING if self.timing else 0) | (FLAG_EVENTS_RESIDENT if self.events_resident else 0)
         return c
 

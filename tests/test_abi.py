@@ -94,7 +94,7 @@ def test_argument_errors_return_before_touching_a_device(lib):
     bad.cell_div = 4
     assert _call(lib, cfg=bad)[0] == ERR
     bad = frnn.FrnnConfig()
-    bad.tile = 48
+    bad.grid_mult = 3
     assert _call(lib, cfg=bad)[0] == ERR
     assert _call(lib, n=2 ** 31)[0] == frnn.FRNN_ERR_UNSUPPORTED
     # n = 0 succeeds with no edges and no device work.

@@ -79,7 +79,8 @@ def test_every_dimension_bucket(d):
 @pytest.mark.parametrize("cfg", [
     frnn.Config(), frnn.Config(dims=(0, 1, 2)), frnn.Config(dims=(2, 0, 5)),
     frnn.Config(cell_div=2), frnn.Config(cell_div=3), frnn.Config(dims=(0, 1, 2), cell_div=2),
-], ids=["default", "lead_dims", "mixed_dims", "div2", "div3", "lead_div2"])
+    frnn.Config(grid_mult=1), frnn.Config(grid_mult=8),
+], ids=["default", "lead_dims", "mixed_dims", "div2", "div3", "lead_div2", "grid1", "grid8"])
 @pytest.mark.parametrize("name", ["tiny", "single"])
 def test_every_config_gives_the_same_edges(cfg, name):
     spec, X, want = event_and_oracle(name)
