@@ -51,9 +51,10 @@ def parse():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-labeling", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run the counter calibration copy and exit")
-    ap.add_argument("--summarize", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "CFETCH", "CWRITE"),
-                    help="print a markdown summary of rocprofv3 output folders and exit")
-    ap.add_argument("--commands", nargs=5, default=["?"] * 5, help="the profiling commands, for the summary")
+    ap.add_argument("--summarize", nargs="+", metavar="DIR",
+                    help="print a markdown summary of rocprofv3 output folders (TRACE FETCH WRITE CFETCH CWRITE "
+                         "[SQ]) and exit")
+    ap.add_argument("--commands", nargs="+", default=None, help="the profiling commands, for the summary")
     return ap.parse_args()
 
 
@@ -119,6 +120,24 @@ def stored_traffic(kernel: str) -> int | None:
     return value if digest == kernel_source_digest() else None
 
 
+def stored_valu(kernel: str) -> float | None:
+    """VALU issue utilisation of `kernel` from the committed counter summary, or
+    None when it is missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    digest = None
+    value = None
+    for line in text.splitlines():
+        if line.startswith("kernel sources sha256/16:"):
+            digest = line.split(":", 1)[1].strip()
+        if line.startswith(f"valu {kernel} issue utilisation:"):
+            value = float(line.split(":", 1)[1].strip())
+    return value if digest == kernel_source_digest() else None
+
+
 def copy_probe() -> None:
     """A plain device copy of 256 MiB, five times: the calibration run for the HBM
     byte counters (FETCH_SIZE / WRITE_SIZE per dispatch against known bytes)."""
@@ -132,10 +151,17 @@ def copy_probe() -> None:
     print(json.dumps({"copy_bytes_per_dispatch": n * 4, "dispatches": 5}), flush=True)
 
 
+# MI355X issue model: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies a
+# SIMD for 4 cycles, at most one per SIMD at a time.
+SIMDS = 1024
+VALU_CYCLES = 4
+
+
 def summarize(trace_dir: str, fetch_dir: str, write_dir: str, cfetch_dir: str, cwrite_dir: str,
-              commands: list[str]) -> str:
-    """Markdown summary of rocprofv3 outputs: kernel durations and HBM bytes per
-    dispatch scaled by the copy calibration."""
+              commands: list[str], sq_dir: str | None = None) -> str:
+    """Markdown summary of rocprofv3 outputs: kernel durations, HBM bytes per
+    dispatch scaled by the copy calibration and, given a folder of SQ/GRBM
+    counters, VALU issue utilisation per kernel."""
     import csv
     import glob
 
@@ -181,6 +207,27 @@ def summarize(trace_dir: str, fetch_dir: str, write_dir: str, cfetch_dir: str, c
     for k in ours:
         b = int(round((fetch[k] * f_scale + write.get(k, 0.0) * w_scale) * 1024))
         lines.append(f"traffic {k} bytes per launch: {b}")
+    if sq_dir is not None:
+        dur = {short(r["Name"]): float(r["AverageNs"]) * 1e-9 for r in rows}
+        sq = {c: counters(sq_dir, c) for c in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+                                             "SQ_INSTS_SMEM")}
+        cmd = commands[5] if len(commands) > 5 else "?"
+        out += ["## VALU issue utilisation", "", f"command: `{cmd}`", "",
+                f"utilisation = SQ_INSTS_VALU x {VALU_CYCLES} cycles / (average duration x 2.4 GHz x {SIMDS} SIMDs): "
+                "the share of the SIMDs' cycles that issued VALU work", "",
+                "| kernel | waves | VALU instr | SALU instr | LDS instr | SMEM instr | VALU util |",
+                "|---|---|---|---|---|---|---|"]
+        vlines = []
+        for k in ours:
+            if k not in sq["SQ_INSTS_VALU"] or k not in dur:
+                continue
+            t = dur[k]
+            util = sq["SQ_INSTS_VALU"][k] * VALU_CYCLES / (t * 2.4e9 * SIMDS)
+            out.append(f"| {k} | {sq['SQ_WAVES'].get(k, 0):.0f} | {sq['SQ_INSTS_VALU'][k]:.0f} | "
+                       f"{sq['SQ_INSTS_SALU'].get(k, 0):.0f} | {sq['SQ_INSTS_LDS'].get(k, 0):.0f} | "
+                       f"{sq['SQ_INSTS_SMEM'].get(k, 0):.0f} | {util:.3f} |")
+            vlines.append(f"valu {k} issue utilisation: {util:.4f}")
+        out += [""] + vlines + [""]
     out += [""] + lines + [""]
     return "\n".join(out)
 
@@ -407,7 +454,11 @@ def labeling_bench(spec, X, pts, steps: int, warmup: int, log, cpu: bool) -> dic
 def main():
     args = parse()
     if args.summarize:
-        print(summarize(*args.summarize, commands=args.commands))
+        if len(args.summarize) not in (5, 6):
+            raise SystemExit("--summarize takes TRACE FETCH WRITE CFETCH CWRITE [SQ]")
+        cmds = args.commands or ["?"] * len(args.summarize)
+        print(summarize(*args.summarize[:5], commands=cmds,
+                        sq_dir=args.summarize[5] if len(args.summarize) == 6 else None))
         return
     if args.copy_probe:
         copy_probe()
@@ -485,6 +536,7 @@ def main():
     roofline = {"bound": "alu", "achieved": ops / t_search / 1e12, "peak": VALU_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": ops / t_search / 1e12 / VALU_PEAK_TOPS,
                 "traffic": stored_traffic("k_search<8, false>") if dpad == 8 and spec.K >= 16 else None,
+                "valu_issue_util": stored_valu("k_search<8, false>") if dpad == 8 and spec.K >= 16 else None,
                 "kernel": "k_search", "kernel_us": t_search * 1e6,
                 "work": f"{st['candidates']} candidate pairs x (3d+1) FP32 ops",
                 "timing": "HIP events on the call's stream around the search kernel, averaged over a second "

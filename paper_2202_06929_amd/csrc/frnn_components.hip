@@ -6,9 +6,14 @@
 //
 // Lock-free union-find on a parent array (one 32-bit entry per vertex):
 //   k_cc_init   parent[v] = v
-//   k_cc_hook   one thread per kept edge: find both roots (path halving), hook
+//   k_cc_hook   one lane per kept edge: find both roots (path halving), hook
 //               the larger root under the smaller one with a compare-and-swap,
-//               retry from the new roots if another thread hooked it first
+//               retry from the new roots if another thread hooked it first.
+//               Edges come grouped by source, so lanes of a wave often share the
+//               source's root; such a group is merged as a star around the
+//               smallest root in it (each lane hooks its own endpoint's root, one
+//               lane hooks the source's), which spreads the compare-and-swaps over
+//               distinct addresses instead of retrying on one
 //   k_cc_label  label[v] = root of v; counts the roots (components)
 // Parent pointers only ever point to smaller ids (hooks go from the larger root
 // to the smaller, halving jumps to an ancestor), so there are no cycles and every
@@ -60,6 +65,66 @@ __device__ unsigned int cc_find(unsigned int *parent, unsigned int x) {
     }
 }
 
+// Roots of x and y, with the two walks interleaved so that their loads overlap.
+__device__ void cc_find2(unsigned int *parent, unsigned int &x, unsigned int &y) {
+    bool dx = false, dy = false;
+    while (!(dx && dy)) {
+        const unsigned int px = dx ? x : ld(parent + x);
+        const unsigned int py = dy ? y : ld(parent + y);
+        dx = dx || px == x;
+        dy = dy || py == y;
+        const unsigned int gx = dx ? x : ld(parent + px);
+        const unsigned int gy = dy ? y : ld(parent + py);
+        if (!dx) {
+            if (gx == px) {
+                x = px;
+                dx = true;
+            } else {
+                st(parent + x, gx);
+                x = gx;
+            }
+        }
+        if (!dy) {
+            if (gy == py) {
+                y = py;
+                dy = true;
+            } else {
+                st(parent + y, gy);
+                y = gy;
+            }
+        }
+    }
+}
+
+// Joins the trees of u and v: hooks the larger root under the smaller with a
+// compare-and-swap.  u and v need not be roots: a failed swap returns the larger
+// vertex's current parent, a strictly smaller id, and the join resumes from its
+// root, so the larger of the pair decreases every round.
+__device__ void cc_union(unsigned int *parent, unsigned int u, unsigned int v, CcState *state) {
+    for (unsigned int round = 0; u != v; ++round) {
+        if (round >= kMaxHookRounds) {
+            atomicOr(&state->status, 2u);
+            return;
+        }
+        const unsigned int hi = u > v ? u : v, lo = u > v ? v : u;
+        unsigned int expected = hi;
+        if (__hip_atomic_compare_exchange_strong(parent + hi, &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        u = cc_find(parent, expected);
+        v = lo;
+    }
+}
+
+__device__ __forceinline__ unsigned int wave_min(unsigned int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned int w = static_cast<unsigned int>(__shfl_xor(static_cast<int>(v), o));
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(kCcBlock) void k_cc_init(unsigned int *parent, long long n, CcState *state) {
     const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
     for (long long v = static_cast<long long>(blockIdx.x) * kCcBlock + threadIdx.x; v < n; v += stride)
@@ -70,34 +135,60 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_init(unsigned int *parent, long
     }
 }
 
+// Groups of lanes sharing a source root handled as stars per wave pass.
+constexpr int kStarGroups = 4;
+
 __global__ __launch_bounds__(kCcBlock) void k_cc_hook(const long long *__restrict__ src,
                                                       const long long *__restrict__ dst, long long n_edges,
                                                       long long n, const float *__restrict__ scores,
                                                       float threshold, unsigned int *parent, CcState *state) {
     const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
-    for (long long e = static_cast<long long>(blockIdx.x) * kCcBlock + threadIdx.x; e < n_edges; e += stride) {
-        if (scores && !(scores[e] > threshold)) continue;
-        const long long a = src[e], b = dst[e];
-        if (a < 0 || a >= n || b < 0 || b >= n) {
-            atomicOr(&state->status, 1u);
-            continue;
-        }
-        if (a == b) continue;
-        unsigned int u = cc_find(parent, static_cast<unsigned int>(a));
-        unsigned int v = cc_find(parent, static_cast<unsigned int>(b));
-        for (unsigned int round = 0; u != v; ++round) {
-            if (round >= kMaxHookRounds) {
-                atomicOr(&state->status, 2u);
-                break;
+    const int lane = static_cast<int>(threadIdx.x & 63u);
+    // The loop runs over wave-aligned bases so that every lane of a wave takes
+    // the same trip count (the star grouping uses whole-wave ballots).
+    for (long long e0 = static_cast<long long>(blockIdx.x) * kCcBlock + (threadIdx.x & ~63u); e0 < n_edges;
+         e0 += stride) {
+        const long long e = e0 + lane;
+        bool act = e < n_edges && !(scores && !(scores[e] > threshold));
+        unsigned int ra = 0u, rb = 0u;
+        if (act) {
+            const long long a = src[e], b = dst[e];
+            if (a < 0 || a >= n || b < 0 || b >= n) {
+                atomicOr(&state->status, 1u);
+                act = false;
+            } else {
+                ra = static_cast<unsigned int>(a);
+                rb = static_cast<unsigned int>(b);
+                cc_find2(parent, ra, rb);
+                act = ra != rb;
             }
-            const unsigned int hi = u > v ? u : v, lo = u > v ? v : u;
-            unsigned int expected = hi;
-            if (__hip_atomic_compare_exchange_strong(parent + hi, &expected, lo, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                break;
-            // hi was hooked meanwhile: continue from its current parent (< hi).
-            u = cc_find(parent, expected);
-            v = lo;
+        }
+        // Star groups: lanes whose source roots agree join every endpoint root of
+        // the group, and the source root, to the smallest of them.
+        unsigned int hub = ra < rb ? ra : rb;
+        bool leader = false, grouped = false;
+        unsigned long long pend = __builtin_amdgcn_ballot_w64(act);
+        for (int g = 0; g < kStarGroups && pend != 0ull; ++g) {
+            const int lead = __builtin_ctzll(pend);
+            const unsigned int r0 = __builtin_amdgcn_readlane(ra, lead);
+            const unsigned long long grp = __builtin_amdgcn_ballot_w64(ra == r0) & pend;
+            const bool mine = (grp >> lane) & 1ull;
+            unsigned int m = wave_min(mine ? rb : 0xffffffffu);
+            m = m < r0 ? m : r0;
+            if (mine) {
+                hub = m;
+                grouped = true;
+                leader = lane == lead;
+            }
+            pend &= ~grp;
+        }
+        if (act) {
+            if (grouped) {
+                cc_union(parent, rb, hub, state);
+                if (leader) cc_union(parent, ra, hub, state);
+            } else {
+                cc_union(parent, ra, rb, state);
+            }
         }
     }
 }
