@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                                    Counters *__restrict__ ctr,
                                                    unsigned long long *__restrict__ tested_out,
                                                    unsigned int *__restrict__ capped_out) {
-    __shared__ unsigned int lst_all[kWaves][kQTile * kListCap];
+    __shared__ __align__(16) unsigned int lst_all[kWaves][kQTile * kListCap];
     __shared__ unsigned int lstd_all[SEL ? kWaves : 1][SEL ? kQTile * kListCap : 1];  // D bits of each hit
     __shared__ unsigned long long thr_all[SEL ? kWaves : 1][SEL ? kQTile : 1];       // K-th smallest (D, j) key
     __shared__ unsigned int pre_all[kWaves][kQTile + 1];
@@ -707,10 +707,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
                 tested += static_cast<unsigned long long>(Qn) * M;
                 wave_lds_sync();
-                // Kept counts for every query; lists that fit are sorted by neighbour id
-                // (after the K nearest are chosen, when the cap binds) and stored at a
-                // fixed place (kListCap slots per sorted row); longer ones go to the
-                // long-list kernel.
+                // Kept counts for every query; lists that fit are stored at a fixed place
+                // (kListCap slots per sorted row), longer ones go to the long-list kernel.
                 const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
                                   (SEL || cnt <= static_cast<unsigned int>(K));
                 if (lane < Qn) {
@@ -730,14 +728,22 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         heavy[h] = he;
                     }
                 }
-                // Sort the lists that fit together: the entries of all lists of the tile
-                // are numbered through a prefix over list lengths; each lane takes one
-                // entry, finds its query by binary search and its rank by counting the
-                // smaller entries of the same list.  With the cap binding, a first pass
-                // finds each list's K-th smallest (D, j) key (D >= 0, so its bits order
-                // like the value) and the entries above it are dropped.
-                {
-                    const unsigned int take = fits ? cnt : 0u;
+                // Lists that fit go to their fixed place (kListCap slots per sorted row)
+                // as found, in 16-byte pieces; the placement pass orders every such list
+                // by neighbour id.  With the cap binding (SEL and more than K hits), the
+                // entries of those lists are numbered through a prefix over their
+                // lengths; a first pass finds each list's K-th smallest (D, j) key (D >= 0,
+                // so its bits order like the value) and each lane then takes one entry,
+                // finds its query by binary search and, if the entry is among the K
+                // nearest, writes it at its rank by neighbour id among them.
+                const unsigned int Ku = static_cast<unsigned int>(K);
+                if (fits && !(SEL && cnt > Ku)) {
+                    const uint4 *from = reinterpret_cast<const uint4 *>(lst + lane * kListCap);
+                    uint4 *to = reinterpret_cast<uint4 *>(temp + static_cast<size_t>(q0 + lane) * kListCap);
+                    for (unsigned int k = 0; 4u * k < cnt; ++k) to[k] = from[k];
+                }
+                if (SEL) {
+                    const unsigned int take = fits && cnt > Ku ? cnt : 0u;
                     const unsigned int inc = wave_inclusive_scan(take);
                     const unsigned int T = __builtin_amdgcn_readlane(inc, 63);
                     if (lane < Qn) {
@@ -754,48 +760,37 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         }
                         return lo;
                     };
-                    const unsigned int Ku = static_cast<unsigned int>(K);
-                    if (SEL) {
-                        for (unsigned int t0 = 0; t0 < T; t0 += 64) {
-                            const unsigned int t = t0 + lane;
-                            if (t < T) {
-                                const int lo = entry_query(t);
-                                const unsigned int cq = tcnt[lo];
-                                if (cq > Ku) {
-                                    const unsigned int *l = lst + lo * kListCap;
-                                    const unsigned int *ld = lstd + lo * kListCap;
-                                    const unsigned int x = t - tpre[lo];
-                                    const unsigned long long key =
-                                        (static_cast<unsigned long long>(ld[x]) << 32) | l[x];
-                                    unsigned int sr = 0;
-                                    for (unsigned int u = 0; u < cq; ++u)
-                                        sr += ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) < key ? 1u : 0u;
-                                    if (sr == Ku - 1u) thr[lo] = key;
-                                }
-                            }
-                        }
-                        wave_lds_sync();
-                    }
                     for (unsigned int t0 = 0; t0 < T; t0 += 64) {
                         const unsigned int t = t0 + lane;
                         if (t < T) {
                             const int lo = entry_query(t);
                             const unsigned int cq = tcnt[lo];
                             const unsigned int *l = lst + lo * kListCap;
+                            const unsigned int *ld = lstd + lo * kListCap;
+                            const unsigned int x = t - tpre[lo];
+                            const unsigned long long key = (static_cast<unsigned long long>(ld[x]) << 32) | l[x];
+                            unsigned int sr = 0;
+                            for (unsigned int u = 0; u < cq; ++u)
+                                sr += ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) < key ? 1u : 0u;
+                            if (sr == Ku - 1u) thr[lo] = key;
+                        }
+                    }
+                    wave_lds_sync();
+                    for (unsigned int t0 = 0; t0 < T; t0 += 64) {
+                        const unsigned int t = t0 + lane;
+                        if (t < T) {
+                            const int lo = entry_query(t);
+                            const unsigned int cq = tcnt[lo];
+                            const unsigned int *l = lst + lo * kListCap;
+                            const unsigned int *ld = lstd + lo * kListCap;
                             const unsigned int x = t - tpre[lo];
                             const unsigned int j = l[x];
-                            unsigned int rk = 0;
-                            if (SEL && cq > Ku) {
-                                const unsigned int *ld = lstd + lo * kListCap;
-                                const unsigned long long lim = thr[lo];
-                                if (((static_cast<unsigned long long>(ld[x]) << 32) | j) <= lim) {
-                                    for (unsigned int u = 0; u < cq; ++u)
-                                        rk += (l[u] < j && ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) <= lim)
-                                                  ? 1u : 0u;
-                                    temp[static_cast<size_t>(q0 + lo) * kListCap + rk] = j;
-                                }
-                            } else {
-                                for (unsigned int u = 0; u < cq; ++u) rk += l[u] < j ? 1u : 0u;
+                            const unsigned long long lim = thr[lo];
+                            if (((static_cast<unsigned long long>(ld[x]) << 32) | j) <= lim) {
+                                unsigned int rk = 0;
+                                for (unsigned int u = 0; u < cq; ++u)
+                                    rk += (l[u] < j && ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) <= lim)
+                                              ? 1u : 0u;
                                 temp[static_cast<size_t>(q0 + lo) * kListCap + rk] = j;
                             }
                         }
@@ -992,9 +987,12 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
 // kKeptGroup tiles, then the tiles of its own group); a block scan of its kept
 // counts gives each query's offset.  Output positions are then mapped to their
 // query through an owner table in LDS, a window at a time, so that consecutive
-// threads write consecutive int64 positions.  Indices are made local to each
-// query's event.  Block 0 writes the report and the status; the block holding an
-// event's first row writes its edge offset.
+// threads handle consecutive int64 positions.  Lists in the fixed kListCap-slot
+// places come from the search in the order their hits were found: a thread reads
+// its entry's whole list (four 16-byte loads) and writes the entry at its rank by
+// neighbour id.  Long lists come sorted from the long-list kernel.  Indices are
+// made local to each query's event.  Block 0 writes the report and the status; the
+// block holding an event's first row writes its edge offset.
 __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const EventDesc *__restrict__ ev,
                                                        int n_events, const unsigned int *__restrict__ kept,
                                                        const unsigned long long *__restrict__ sums_kept,
@@ -1098,6 +1096,8 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     }
     const unsigned int total = o[cnt];
     if (pre + total > cap) return;  // cannot happen when E <= cap; never write past the outputs
+    // End of the fixed list places; long lists live after it.
+    const unsigned long long fixed_end = static_cast<unsigned long long>(rows) * kListCap;
     for (unsigned int w0 = 0; w0 < total; w0 += kOwnerWindow) {
         const unsigned int wend = total - w0 < kOwnerWindow ? total - w0 : kOwnerWindow;
         if (q < cnt) {
@@ -1109,12 +1109,39 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
         for (unsigned int p = threadIdx.x; p < wend; p += kPlaceBlock) {
             const int r = owner[p];
             const unsigned int pos = w0 + p;
-            const long long out = static_cast<long long>(pre) + pos;
-            const unsigned long long tix = tp[r] + (pos - o[r]);
-            src[out] = i0 + r - base_row[r];
-            // The list positions come from the search; the bound only keeps a
+            const unsigned int k = pos - o[r];
+            const unsigned int len = o[r + 1] - o[r];
+            const unsigned long long t0 = tp[r];
+            src[static_cast<long long>(pre) + pos] = i0 + r - base_row[r];
+            // The list positions come from the search; the bounds only keep a
             // corrupted position from reading outside the workspace.
-            dst[out] = tix < temp_len ? static_cast<long long>(temp[tix]) - base_row[r] : -1ll;
+            unsigned int rank = k;
+            long long v = -1ll;
+            if (t0 < fixed_end) {
+                if (t0 + kListCap <= temp_len) {
+                    const uint4 *l4 = reinterpret_cast<const uint4 *>(temp + t0);
+                    unsigned int l[kListCap];
+#pragma unroll
+                    for (int c = 0; c < kListCap / 4; ++c) {
+                        const uint4 w = l4[c];
+                        l[4 * c] = w.x;
+                        l[4 * c + 1] = w.y;
+                        l[4 * c + 2] = w.z;
+                        l[4 * c + 3] = w.w;
+                    }
+                    unsigned int x = l[0];
+#pragma unroll
+                    for (int u = 1; u < kListCap; ++u) x = k == static_cast<unsigned int>(u) ? l[u] : x;
+                    rank = 0;
+#pragma unroll
+                    for (int u = 0; u < kListCap; ++u)
+                        rank += (static_cast<unsigned int>(u) < len && l[u] < x) ? 1u : 0u;
+                    v = static_cast<long long>(x) - base_row[r];
+                }
+            } else if (t0 + k < temp_len) {
+                v = static_cast<long long>(temp[t0 + k]) - base_row[r];
+            }
+            dst[static_cast<long long>(pre) + o[r] + rank] = v;
         }
         __syncthreads();
     }
