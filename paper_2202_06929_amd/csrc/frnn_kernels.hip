@@ -554,7 +554,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     __shared__ unsigned int pre_all[kWaves][kQTile + 1];
     __shared__ unsigned int cnt_all[kWaves][kQTile];
     __shared__ unsigned int qcnt_all[kWaves][kQTile];
-    __shared__ unsigned long long ring_all[kWaves][kRing];  // (q << 6 | lane) << 32 | bits of the partial sum
+    // Row-addressed entries: q << 32 | candidate row, with the partial sum in racc;
+    // lane-addressed entries: (q << 6 | lane) << 32 | bits of the partial sum.
+    __shared__ unsigned long long ring_all[kWaves][kRing];
+    __shared__ float racc_all[DP <= 8 ? kWaves : 1][DP <= 8 ? kRing : 1];
     __shared__ unsigned long long tested_w[kWaves];
     __shared__ unsigned int capped_w[kWaves];
     if (ctr->abort) return;
@@ -566,10 +569,14 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned int *tcnt = cnt_all[wave_id()];
     unsigned int *qcnt = qcnt_all[wave_id()];
     unsigned long long *ring = ring_all[wave_id()];
+    float *racc = racc_all[DP <= 8 ? wave_id() : 0];
     const int lane = lane_id();
     const unsigned int total_waves = gridDim.x * kWaves;
     constexpr int kLead = DP < 3 ? DP : 3;  // terms before the first exact rejection test
-    constexpr int kPre = DP < 16 ? DP : 16;  // coordinates of a query row held in registers
+    // Row-addressed ring entries (the entry names the candidate's sorted row and the
+    // remaining coordinates are loaded when the entry is finished) for rows of up to
+    // 8 floats; wider rows exchange the candidate's coordinates between lanes instead.
+    constexpr bool kRowRing = DP <= 8;
     unsigned long long tested = 0;
 
     // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
@@ -610,10 +617,12 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 const int Qn = static_cast<int>(min(static_cast<unsigned int>(kQTile), qe - q0));
                 if (lane < kQTile) qcnt[lane] = 0u;
                 // Candidate rows are fetched one chunk ahead so that their latency
-                // overlaps the tests of the current chunk.  Idle lanes read row 0 (any
-                // row is a valid address) and are masked out of every ballot.
-                float cn[DP];
-                unsigned int sn, jn;
+                // overlaps the tests of the current chunk (with row-addressed ring entries
+                // only the leading coordinates, one 16-byte load).  Idle lanes read row 0
+                // (any row is a valid address) and are masked out of every ballot.
+                constexpr int kHeld = kRowRing ? 4 : DP;  // candidate coordinates held per lane
+                float cn[kHeld];
+                unsigned int sn, jn = 0u;
                 // rc: the run holding candidate b (wave-uniform).  Runs are consecutive
                 // ranges of candidates, so only the runs that start inside the chunk
                 // need to be compared with each lane's candidate number.
@@ -631,70 +640,112 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     const unsigned int srow = static_cast<unsigned int>(__shfl(start, r)) +
                                               (m - static_cast<unsigned int>(__shfl(pre, r)));
                     sn = mm < M ? srow : 0u;
-                    load_row<DP>(sorted, sn, cn);
-                    jn = sorted_id[sn];
+                    if constexpr (kRowRing) {
+                        const float4 v = *reinterpret_cast<const float4 *>(sorted + static_cast<size_t>(sn) * DP);
+                        cn[0] = v.x;
+                        cn[1] = v.y;
+                        cn[2] = v.z;
+                        cn[3] = v.w;
+                    } else {
+                        load_row<DP>(sorted, sn, cn);
+                        jn = sorted_id[sn];
+                    }
+                };
+                // A pair that passes the full test joins query q's list.
+                auto keep = [&](bool pass, unsigned int q, unsigned int j, float D) {
+                    if (pass) {
+                        const unsigned int pos = atomicAdd(&qcnt[q], 1u);
+                        if (pos < static_cast<unsigned int>(kListCap)) {
+                            lst[q * kListCap + pos] = j;
+                            if (SEL) lstd[q * kListCap + pos] = __float_as_uint(D);
+                        }
+                    }
+                };
+                // Second stage for ring entries [h, h + nb): lane l takes entry h + l and
+                // adds terms kLead.. of the definition to the first stage's partial sum,
+                // in the same order.  A row-addressed entry names its candidate row (the
+                // remaining coordinates are loaded); a lane-addressed entry (below) names
+                // the lane of the current chunk that holds the candidate.
+                auto finish_rows = [&](unsigned int h, unsigned int nb) {
+                    wave_lds_sync();
+                    const bool act = static_cast<unsigned int>(lane) < nb;
+                    const unsigned int e = (h + lane) & (kRing - 1);
+                    const unsigned long long ent = act ? ring[e] : 0ull;
+                    const float a3 = act ? racc[e] : 0.0f;
+                    const unsigned int q = static_cast<unsigned int>(ent >> 32);
+                    const unsigned int s2 = static_cast<unsigned int>(ent);
+                    const float *crow = sorted + static_cast<size_t>(s2) * DP;
+                    float cc[DP];
+#pragma unroll
+                    for (int k = kLead; k < DP; ++k) cc[k] = crow[k];
+                    const unsigned int j2 = sorted_id[s2];
+                    const float D = add_terms<kLead, DP, DP>(a3, cc, sorted + static_cast<size_t>(q0 + q) * DP);
+                    keep(act && D < r2 && s2 != q0 + q, q, j2, D);
+                    wave_lds_sync();
                 };
                 fetch(0u);
+                unsigned int head = 0, tail = 0;
                 for (unsigned int base = 0; base < M; base += 64) {
                     const bool valid = base + lane < M;
-                    float c[DP];
+                    float c[kHeld];
 #pragma unroll
-                    for (int k = 0; k < DP; ++k) c[k] = cn[k];
+                    for (int k = 0; k < kHeld; ++k) c[k] = cn[k];
                     const unsigned int s = sn, jid = jn;
                     if (base + 64 < M) fetch(base + 64);
                     const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
-                    // Second stage for ring entries [h, h + nb): lane l finishes the sum of
-                    // entry h + l (candidate lane cl, query q) from the three-term partial
-                    // sum, in the same order as the first stage began it.
+                    // Lane-addressed entries: the candidate's coordinates are exchanged
+                    // between lanes of the current chunk.
                     auto finish = [&](unsigned int h, unsigned int nb) {
-                        wave_lds_sync();
-                        const bool act = static_cast<unsigned int>(lane) < nb;
-                        const unsigned int e = (h + lane) & (kRing - 1);
-                        const unsigned long long ent = act ? ring[e] : 0ull;
-                        const unsigned int code = static_cast<unsigned int>(ent >> 32);
-                        float acc = __uint_as_float(static_cast<unsigned int>(ent));
-                        const int cl = static_cast<int>(code & 63u);
-                        const unsigned int q = code >> 6;
-                        float cc[DP];
+                        if constexpr (kRowRing) {
+                            finish_rows(h, nb);
+                        } else {
+                            wave_lds_sync();
+                            const bool act = static_cast<unsigned int>(lane) < nb;
+                            const unsigned int e = (h + lane) & (kRing - 1);
+                            const unsigned long long ent = act ? ring[e] : 0ull;
+                            float cc[DP];
+                            const unsigned int code = static_cast<unsigned int>(ent >> 32);
+                            const int cl = static_cast<int>(code & 63u);
+                            const unsigned int q = code >> 6;
 #pragma unroll
-                        for (int k = kLead; k < DP; ++k) cc[k] = __shfl(c[k], cl);
-                        const unsigned int s2 = static_cast<unsigned int>(__shfl(static_cast<int>(s), cl));
-                        const unsigned int j2 = static_cast<unsigned int>(__shfl(static_cast<int>(jid), cl));
-                        acc = add_terms<kLead, DP, DP>(acc, cc, sorted + static_cast<size_t>(q0 + q) * DP);
-                        if (act && acc < r2 && s2 != q0 + q) {
-                            const unsigned int pos = atomicAdd(&qcnt[q], 1u);
-                            if (pos < static_cast<unsigned int>(kListCap)) {
-                                lst[q * kListCap + pos] = j2;
-                                if (SEL) lstd[q * kListCap + pos] = __float_as_uint(acc);
-                            }
+                            for (int k = kLead; k < DP; ++k) cc[k] = __shfl(c[k], cl);
+                            const unsigned int s2 = static_cast<unsigned int>(__shfl(static_cast<int>(s), cl));
+                            const unsigned int j2 = static_cast<unsigned int>(__shfl(static_cast<int>(jid), cl));
+                            const float D = add_terms<kLead, DP, DP>(__uint_as_float(static_cast<unsigned int>(ent)),
+                                                                     cc, sorted + static_cast<size_t>(q0 + q) * DP);
+                            keep(act && D < r2 && s2 != q0 + q, q, j2, D);
+                            wave_lds_sync();
                         }
-                        wave_lds_sync();
                     };
                     // Query rows are wave-uniform (scalar loads); the next one is
                     // requested before the current one is tested.
-                    float qn[kPre];
+                    float qn[kLead];
 #pragma unroll
-                    for (int k = 0; k < kPre; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
-                    unsigned int head = 0, tail = 0;
+                    for (int k = 0; k < kLead; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
                     for (int q = 0; q < Qn; ++q) {
                         const float *qrow = sorted + static_cast<size_t>(q0 + q) * DP;
-                        float qc[kPre];
+                        float qc[kLead];
 #pragma unroll
-                        for (int k = 0; k < kPre; ++k) qc[k] = qn[k];
+                        for (int k = 0; k < kLead; ++k) qc[k] = qn[k];
                         if (q + 1 < Qn) {
 #pragma unroll
-                            for (int k = 0; k < kPre; ++k) qn[k] = qrow[DP + k];
+                            for (int k = 0; k < kLead; ++k) qn[k] = qrow[DP + k];
                         }
                         // First stage: three terms for all 64 candidates; pairs that are not
                         // yet at r2 are queued (exact: the remaining terms only add).
-                        const float acc = add_terms_r<0, kLead, DP, kPre>(0.0f, c, qc);
+                        const float acc = add_terms_r<0, kLead, kHeld, kLead>(0.0f, c, qc);
                         const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2) & vmask;
                         if (m1 == 0ull) continue;
                         if (valid && acc < r2) {
                             const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
-                            ring[e] = (static_cast<unsigned long long>((static_cast<unsigned int>(q) << 6) |
-                                                                      static_cast<unsigned int>(lane)) << 32) |
-                                      __float_as_uint(acc);
+                            if constexpr (kRowRing) {
+                                ring[e] = (static_cast<unsigned long long>(q) << 32) | s;
+                                racc[e] = acc;
+                            } else {
+                                ring[e] = (static_cast<unsigned long long>((static_cast<unsigned int>(q) << 6) |
+                                                                          static_cast<unsigned int>(lane)) << 32) |
+                                          __float_as_uint(acc);
+                            }
                         }
                         tail += static_cast<unsigned int>(__popcll(m1));
                         if (tail - head >= 64u) {
@@ -702,7 +753,14 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                             head += 64u;
                         }
                     }
-                    if (tail != head) finish(head, tail - head);
+                    // Lane-addressed entries refer to this chunk's registers: drain them now.
+                    if (!kRowRing && tail != head) {
+                        finish(head, tail - head);
+                        head = tail;
+                    }
+                }
+                if constexpr (kRowRing) {
+                    if (tail != head) finish_rows(head, tail - head);
                 }
                 const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
                 tested += static_cast<unsigned long long>(Qn) * M;
