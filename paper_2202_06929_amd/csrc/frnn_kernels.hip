@@ -614,7 +614,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
             unsigned int start, pre;
             const unsigned int M = wave_runs(cell - cell0, cell0, P, cell_start, start, pre);
             for (unsigned int q0 = qs; q0 < qe; q0 += kQTile) {
-                const int Qn = static_cast<int>(min(static_cast<unsigned int>(kQTile), qe - q0));
+                const int Qn = static_cast<int>(uniform(min(static_cast<unsigned int>(kQTile), qe - q0)));
                 if (lane < kQTile) qcnt[lane] = 0u;
                 // Candidate rows are fetched one chunk ahead so that their latency
                 // overlaps the tests of the current chunk (with row-addressed ring entries
@@ -722,8 +722,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     float qn[kLead];
 #pragma unroll
                     for (int k = 0; k < kLead; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
-                    for (int q = 0; q < Qn; ++q) {
-                        const float *qrow = sorted + static_cast<size_t>(q0 + q) * DP;
+                    const float *qrow = sorted + static_cast<size_t>(q0) * DP;
+                    for (int q = 0; q < Qn; ++q, qrow += DP) {
                         float qc[kLead];
 #pragma unroll
                         for (int k = 0; k < kLead; ++k) qc[k] = qn[k];
@@ -739,7 +739,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         if (valid && acc < r2) {
                             const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
                             if constexpr (kRowRing) {
-                                ring[e] = (static_cast<unsigned long long>(q) << 32) | s;
+                                ring[e] = (static_cast<unsigned long long>(uniform(static_cast<unsigned int>(q))) << 32) | s;
                                 racc[e] = acc;
                             } else {
                                 ring[e] = (static_cast<unsigned long long>((static_cast<unsigned int>(q) << 6) |
