@@ -124,7 +124,8 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     const int64_t groups_kept = (tiles_kept + kKeptGroup - 1) / kKeptGroup;
     ws.sums_kept = cv.take<unsigned long long>(tiles_kept);
     ws.sums_kept2 = cv.take<unsigned long long>(groups_kept);
-    ws.sorted = cv.take<float>(static_cast<size_t>(rows) * dpad);
+    // One padding row after the last: the search requests the row after each query.
+    ws.sorted = cv.take<float>(static_cast<size_t>(rows + 1) * dpad);
     ws.sorted_id = cv.take<unsigned int>(rows);
     ws.sorted_key = cv.take<unsigned int>(rows);
     ws.kept = cv.take<unsigned int>(rows);

@@ -650,6 +650,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         load_row<DP>(sorted, sn, cn);
                         jn = sorted_id[sn];
                     }
+                    // Lanes past the last candidate fail every first-stage test.
+                    if (mm >= M) cn[0] = INFINITY;
                 };
                 // A pair that passes the full test joins query q's list.
                 auto keep = [&](bool pass, unsigned int q, unsigned int j, float D) {
@@ -686,13 +688,11 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 fetch(0u);
                 unsigned int head = 0, tail = 0;
                 for (unsigned int base = 0; base < M; base += 64) {
-                    const bool valid = base + lane < M;
                     float c[kHeld];
 #pragma unroll
                     for (int k = 0; k < kHeld; ++k) c[k] = cn[k];
                     const unsigned int s = sn, jid = jn;
                     if (base + 64 < M) fetch(base + 64);
-                    const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
                     // Lane-addressed entries: the candidate's coordinates are exchanged
                     // between lanes of the current chunk.
                     auto finish = [&](unsigned int h, unsigned int nb) {
@@ -718,7 +718,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         }
                     };
                     // Query rows are wave-uniform (scalar loads); the next one is
-                    // requested before the current one is tested.
+                    // requested before the current one is tested (the sorted rows end with
+                    // one padding row, so the request after the last query stays in bounds).
                     float qn[kLead];
 #pragma unroll
                     for (int k = 0; k < kLead; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
@@ -727,16 +728,14 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         float qc[kLead];
 #pragma unroll
                         for (int k = 0; k < kLead; ++k) qc[k] = qn[k];
-                        if (q + 1 < Qn) {
 #pragma unroll
-                            for (int k = 0; k < kLead; ++k) qn[k] = qrow[DP + k];
-                        }
+                        for (int k = 0; k < kLead; ++k) qn[k] = qrow[DP + k];
                         // First stage: three terms for all 64 candidates; pairs that are not
                         // yet at r2 are queued (exact: the remaining terms only add).
                         const float acc = add_terms_r<0, kLead, kHeld, kLead>(0.0f, c, qc);
-                        const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2) & vmask;
+                        const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2);
                         if (m1 == 0ull) continue;
-                        if (valid && acc < r2) {
+                        if (acc < r2) {
                             const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
                             if constexpr (kRowRing) {
                                 ring[e] = (static_cast<unsigned long long>(uniform(static_cast<unsigned int>(q))) << 32) | s;
