@@ -8,16 +8,19 @@
 //                 histogram with in-cell arrival rank, per-tile histogram totals
 //   k_scan_tiles  exclusive scan of the histogram -> first sorted row of each cell
 //   k_scatter     counting-sort scatter: rows copied into cell order
-//   k_search      one wave per cell: the cell's queries against the (2R+1)^2
-//                 contiguous x-runs of neighbouring cells; each lane holds one
-//                 candidate row in registers, query rows are wave-uniform; an exact
-//                 early exit after the first three terms of the distance sum; wave
-//                 ballots collect hits; each list is sorted and stored
+//   k_search      each wave takes an equal share of the queries in cell order: a
+//                 cell's queries against the (2R+1)^2 contiguous x-runs of
+//                 neighbouring cells; each lane holds one candidate (its leading
+//                 coordinates, or its whole row for rows wider than 8 floats), query
+//                 rows are wave-uniform; an exact early exit after the first two or
+//                 three terms of the distance sum; ballots queue the survivors, whose
+//                 sums are finished 64 at a time; each list is stored as found
 //   k_heavy       kept totals per tile and per group of tiles; queries whose list
 //                 is longer than the search keeps, or longer than K: the K smallest
 //                 by (D, j) found by an MSB-first radix select
-//   k_place       output offsets from the totals and a block scan; edges written to
-//                 their (i asc, j asc) positions with coalesced stores
+//   k_place       output offsets from the totals and a block scan; each list entry
+//                 ranked within its list and the edges written to their
+//                 (i asc, j asc) positions
 //
 // Distances follow one fixed order with every product and sum rounded on its
 // own: this file is compiled with -ffp-contract=off and the pragma below.
@@ -572,7 +575,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     float *racc = racc_all[DP <= 8 ? wave_id() : 0];
     const int lane = lane_id();
     const unsigned int total_waves = gridDim.x * kWaves;
-    constexpr int kLead = DP < 3 ? DP : 3;  // terms before the first exact rejection test
+    // Terms before the first exact rejection test: two for rows of up to 8 floats
+    // (their three-term test rejects few more pairs than two terms do, and the
+    // first stage runs for every query and candidate), three for wider rows.
+    constexpr int kLead = DP <= 8 ? 2 : 3;
     // Row-addressed ring entries (the entry names the candidate's sorted row and the
     // remaining coordinates are loaded when the entry is finished) for rows of up to
     // 8 floats; wider rows exchange the candidate's coordinates between lanes instead.
@@ -730,7 +736,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         for (int k = 0; k < kLead; ++k) qc[k] = qn[k];
 #pragma unroll
                         for (int k = 0; k < kLead; ++k) qn[k] = qrow[DP + k];
-                        // First stage: three terms for all 64 candidates; pairs that are not
+                        // First stage: kLead terms for all 64 candidates; pairs that are not
                         // yet at r2 are queued (exact: the remaining terms only add).
                         const float acc = add_terms_r<0, kLead, kHeld, kLead>(0.0f, c, qc);
                         const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2);
