@@ -6,7 +6,9 @@
 //
 // Lock-free union-find on a parent array (one 32-bit entry per vertex):
 //   k_cc_init   parent[v] = v
-//   k_cc_hook   one lane per kept edge: find both roots (path halving), hook
+//   k_cc_hook   one lane per kept edge: find both roots (plain reads: the only
+//               writes of this kernel are the hooks, device-scope atomics that are
+//               performed beyond the per-XCD caches and cost memory traffic), hook
 //               the larger root under the smaller one with a compare-and-swap,
 //               retry from the new roots if another thread hooked it first.
 //               Edges come grouped by source, so lanes of a wave often share the
@@ -14,7 +16,7 @@
 //               smallest root in it (each lane hooks its own endpoint's root, one
 //               lane hooks the source's), which spreads the compare-and-swaps over
 //               distinct addresses instead of retrying on one
-//   k_cc_label  label[v] = root of v; counts the roots (components)
+//   k_cc_label  label[v] = root of v (path halving); counts the roots
 // Parent pointers only ever point to smaller ids (hooks go from the larger root
 // to the smaller, halving jumps to an ancestor), so there are no cycles and every
 // find ends.  When all edges are done each component is one tree, and its root is
@@ -25,7 +27,8 @@
 // prove two vertices share a tree.  Hooks are device-scope compare-and-swaps on
 // the presumed root; a failed one returns that vertex's current parent, a
 // strictly smaller id, and the hook resumes from there, so every retry makes
-// progress on fresh data.  Path-halving stores are device-scope atomic stores.
+// progress on fresh data.  Path-halving stores (labeling pass) are device-scope
+// atomic stores.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -65,7 +68,17 @@ __device__ unsigned int cc_find(unsigned int *parent, unsigned int x) {
     }
 }
 
-// Roots of x and y, with the two walks interleaved so that their loads overlap.
+// Root of x by plain reads (no path halving).
+__device__ __forceinline__ unsigned int cc_root(unsigned int *parent, unsigned int x) {
+    for (;;) {
+        const unsigned int p = ld(parent + x);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+// Roots of x and y by plain reads, the two walks interleaved so that their loads
+// overlap.
 __device__ void cc_find2(unsigned int *parent, unsigned int &x, unsigned int &y) {
     bool dx = false, dy = false;
     while (!(dx && dy)) {
@@ -80,7 +93,6 @@ __device__ void cc_find2(unsigned int *parent, unsigned int &x, unsigned int &y)
                 x = px;
                 dx = true;
             } else {
-                st(parent + x, gx);
                 x = gx;
             }
         }
@@ -89,7 +101,6 @@ __device__ void cc_find2(unsigned int *parent, unsigned int &x, unsigned int &y)
                 y = py;
                 dy = true;
             } else {
-                st(parent + y, gy);
                 y = gy;
             }
         }
@@ -111,7 +122,7 @@ __device__ void cc_union(unsigned int *parent, unsigned int u, unsigned int v, C
         if (__hip_atomic_compare_exchange_strong(parent + hi, &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT))
             return;
-        u = cc_find(parent, expected);
+        u = cc_root(parent, expected);
         v = lo;
     }
 }
