@@ -130,3 +130,15 @@ def test_async_and_captured_graph_replays_match():
         assert res[1].item() == 0, f"replay {rep}"
         assert res[0].item() == len(np.unique(want))
         assert np.array_equal(lab.cpu().numpy(), want), f"replay {rep}"
+
+
+def test_no_vertices():
+    # No labeling pass runs; the count and the status still reach the caller.
+    empty = torch.zeros(0, dtype=torch.int64, device=DEV)
+    lab, nc = frnn.components(empty, empty, 0)
+    torch.cuda.synchronize()
+    assert lab.numel() == 0 and nc == 0
+    one = torch.zeros(1, dtype=torch.int64, device=DEV)
+    with pytest.raises(frnn.FrnnError) as e:
+        frnn.components(one, one, 0)
+    assert e.value.status == frnn.FRNN_ERR_ARG
