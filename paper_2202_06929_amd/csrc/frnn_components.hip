@@ -16,8 +16,7 @@
 //               smallest root in it (each lane hooks its own endpoint's root, one
 //               lane hooks the source's), which spreads the compare-and-swaps over
 //               distinct addresses instead of retrying on one
-//   k_cc_label  label[v] = root of v (path halving); counts the roots, and the
-//               last workgroup to finish writes the count and the status
+//   k_cc_label  label[v] = root of v (path halving); counts the roots
 // Parent pointers only ever point to smaller ids (hooks go from the larger root
 // to the smaller, halving jumps to an ancestor), so there are no cycles and every
 // find ends.  When all edges are done each component is one tree, and its root is
@@ -47,7 +46,7 @@ constexpr unsigned int kMaxHookRounds = 1u << 20;
 
 struct CcState {
     unsigned int status;             // bit 0: endpoint out of range; bit 1: hook bound reached
-    unsigned int done;               // labeling workgroups finished
+    unsigned int pad;
     unsigned long long n_components;
 };
 
@@ -205,17 +204,8 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_hook(const long long *__restric
     }
 }
 
-__device__ __forceinline__ void write_result(const CcState *state, long long *result) {
-    const unsigned int s = __hip_atomic_load(&state->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    result[0] = static_cast<long long>(
-        __hip_atomic_load(&state->n_components, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    result[1] = (s & 1u) ? FRNN_ERR_ARG : ((s & 2u) ? FRNN_ERR_HIP : FRNN_OK);
-}
-
-// Labels and root counts; the last workgroup to finish (counted with a device-scope
-// atomic after its own count is added) writes the caller's result.
 __global__ __launch_bounds__(kCcBlock) void k_cc_label(unsigned int *parent, long long n, long long *labels,
-                                                       CcState *state, long long *result) {
+                                                       CcState *state) {
     __shared__ unsigned long long part[kCcBlock / 64];
     const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
     unsigned long long roots = 0;
@@ -231,17 +221,15 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_label(unsigned int *parent, lon
         unsigned long long t = 0;
         for (int w = 0; w < kCcBlock / 64; ++w) t += part[w];
         if (t) atomicAdd(&state->n_components, t);
-        __threadfence();
-        const unsigned int finished = atomicAdd(&state->done, 1u);
-        if (finished == gridDim.x - 1) {
-            __threadfence();
-            write_result(state, result);
-        }
     }
 }
 
-// The caller's result when there are no vertices (no labeling pass runs).
-__global__ void k_cc_result(const CcState *state, long long *result) { write_result(state, result); }
+// Copies the state into the caller's device result [n_components, status].
+__global__ void k_cc_result(const CcState *state, long long *result) {
+    const unsigned int s = state->status;
+    result[0] = static_cast<long long>(state->n_components);
+    result[1] = (s & 1u) ? FRNN_ERR_ARG : ((s & 2u) ? FRNN_ERR_HIP : FRNN_OK);
+}
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -273,9 +261,8 @@ int enqueue(const int64_t *src, const int64_t *dst, int64_t n_edges, int64_t n_v
                            static_cast<long long>(n_edges), n, scores, threshold, parent, state);
     if (n > 0)
         hipLaunchKernelGGL(k_cc_label, dim3(grid_for(n)), dim3(kCcBlock), 0, s, parent, n,
-                           reinterpret_cast<long long *>(labels), state, reinterpret_cast<long long *>(result_device));
-    else
-        hipLaunchKernelGGL(k_cc_result, dim3(1), dim3(1), 0, s, state, reinterpret_cast<long long *>(result_device));
+                           reinterpret_cast<long long *>(labels), state);
+    hipLaunchKernelGGL(k_cc_result, dim3(1), dim3(1), 0, s, state, reinterpret_cast<long long *>(result_device));
     return hipGetLastError() == hipSuccess ? FRNN_OK : FRNN_ERR_HIP;
 }
 
