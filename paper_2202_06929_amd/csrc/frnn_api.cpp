@@ -210,6 +210,7 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
         if (config && config->grid_mult > 0) m = config->grid_mult;
         const long long b = resident * m;
         a.search_blocks = static_cast<int>(b > kMaxSearchBlocks ? kMaxSearchBlocks : b);
+        a.search_prio = a.search_blocks <= resident ? 1 : 0;
     }
     // About 16 coordinates per thread of the bounds pass, at most kBoundsBlocks blocks per event.
     const long long bb = (static_cast<long long>(max_n) * d + 16 * kBlock - 1) / (16 * kBlock);

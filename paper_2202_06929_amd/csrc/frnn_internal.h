@@ -148,6 +148,7 @@ struct LaunchArgs {
     hipStream_t stream;
     hipEvent_t *events;     // 8 events bracketing the 7 stages, or null
     int search_blocks;      // resident workgroups of the search kernel
+    int search_prio;        // 1: the search grid is one round of resident workgroups
     int bounds_blocks;      // bounds partials per event (<= kBoundsBlocks)
     EventDesc ev0;          // event 0, written to ws.ev by the first kernel when ev_from_arg
     int ev_from_arg;

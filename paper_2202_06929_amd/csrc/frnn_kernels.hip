@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                                    HeavyEntry *__restrict__ heavy,
                                                    Counters *__restrict__ ctr,
                                                    unsigned long long *__restrict__ tested_out,
-                                                   unsigned int *__restrict__ capped_out) {
+                                                   unsigned int *__restrict__ capped_out, int prio) {
     __shared__ __align__(16) unsigned int lst_all[kWaves][kQTile * kListCap];
     __shared__ unsigned int lstd_all[SEL ? kWaves : 1][SEL ? kQTile * kListCap : 1];  // D bits of each hit
     __shared__ unsigned long long thr_all[SEL ? kWaves : 1][SEL ? kQTile : 1];       // K-th smallest (D, j) key
@@ -621,6 +621,20 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
             const unsigned int M = wave_runs(cell - cell0, cell0, P, cell_start, start, pre);
             for (unsigned int q0 = qs; q0 < qe; q0 += kQTile) {
                 const int Qn = static_cast<int>(uniform(min(static_cast<unsigned int>(kQTile), qe - q0)));
+                if (prio) {
+                    // A SIMD issues the oldest ready wave first, so with every workgroup
+                    // resident from the start the waves dispatched last finish last and
+                    // the SIMD runs its final stretch with few waves.  Issue priority
+                    // falls as a wave works off its share (3 in the first quarter, 0 in
+                    // the last), so that waves behind are issued first and the waves of
+                    // a SIMD finish closer together.
+                    const unsigned int left = q_hi - q0;
+                    const unsigned int share = q_hi - q_lo;
+                    if (4u * left > 3u * share) __builtin_amdgcn_s_setprio(3);
+                    else if (4u * left > 2u * share) __builtin_amdgcn_s_setprio(2);
+                    else if (4u * left > share) __builtin_amdgcn_s_setprio(1);
+                    else __builtin_amdgcn_s_setprio(0);
+                }
                 if (lane < kQTile) qcnt[lane] = 0u;
                 // Candidate rows are fetched one chunk ahead so that their latency
                 // overlaps the tests of the current chunk (with row-addressed ring entries
@@ -1227,11 +1241,13 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     if (a.K < kListCap)
         hipLaunchKernelGGL((k_search<DP, true>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
                            ws.sorted_id, ws.sorted_key, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
-                           a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk);
+                           a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
+                           a.search_prio);
     else
         hipLaunchKernelGGL((k_search<DP, false>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
                            ws.sorted_id, ws.sorted_key, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
-                           a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk);
+                           a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
+                           a.search_prio);
     mark(5);
     const unsigned long long heavy_base = static_cast<unsigned long long>(rows) * kListCap;
     const long long hb = (static_cast<long long>(ws.tiles_kept_n) + kWaves - 1) / kWaves;
