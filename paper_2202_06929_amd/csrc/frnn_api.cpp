@@ -199,14 +199,15 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
     a.src = reinterpret_cast<long long *>(src);
     a.dst = reinterpret_cast<long long *>(dst);
     a.stream = stream;
-    // One resident wave per SIMD slot when each gets few rows; with many rows per
-    // wave, up to four times as many workgroups as fit at once, so that the
-    // hardware hands the remaining shares to whichever workgroups finish first.
+    // One round of resident workgroups (whose waves then order their issue by
+    // progress) unless each resident wave would get more than 128 rows; then up to
+    // four times as many workgroups as fit at once, so that the hardware hands the
+    // remaining shares to whichever workgroups finish first.
     {
         const int resident = search_blocks_cached(a.dpad, K < kListCap);
         const long long per_wave = rows / (static_cast<long long>(resident) * kWaves);
-        long long m = per_wave / 24;
-        m = m < 1 ? 1 : (m > 4 ? 4 : m);
+        long long m = per_wave < 128 ? 1 : per_wave / 128 + 1;
+        m = m > 4 ? 4 : m;
         if (config && config->grid_mult > 0) m = config->grid_mult;
         const long long b = resident * m;
         a.search_blocks = static_cast<int>(b > kMaxSearchBlocks ? kMaxSearchBlocks : b);
