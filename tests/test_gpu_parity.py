@@ -305,3 +305,24 @@ def test_large_batch_uses_grouped_offsets():
         assert_same(got, gpu_edges(X, 0.1, 256))
         if e in (0, 8):
             assert_same(got, oracle.frnn_grid(X, 0.1, 256))
+
+
+@pytest.mark.parametrize("grid_mult", [0, 4])
+def test_benchmark_batch_of_64_events(grid_mult):
+    """The benchmark's batch (64 events of 20k-150k hits, binned coordinates 4, 5, 7
+    as the tuner picks them): every event equals the event built alone, and three
+    events (the smallest, the largest and one between) equal the oracle."""
+    sizes = events.batched_sizes()
+    evs = [events.generate(events.batched_spec(n, 100 + k))[0] for k, n in enumerate(sizes)]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pts = torch.from_numpy(np.concatenate(evs)).to(DEV)
+    cfg = frnn.Config(dims=(4, 5, 7), grid_mult=grid_mult)
+    log(f"benchmark batch: {offsets[-1]} rows, grid_mult {grid_mult}")
+    edges, eo = frnn.build_batch(pts, offsets, 0.1, 256, cfg)
+    edges = edges.cpu().numpy()
+    sampled = {int(np.argmin(sizes)), int(np.argmax(sizes)), 31}
+    for e, X in enumerate(evs):
+        got = np.ascontiguousarray(edges[:, eo[e]:eo[e + 1]])
+        assert_same(got, gpu_edges(X, 0.1, 256))
+        if e in sampled:
+            assert_same(got, oracle.frnn_grid(X, 0.1, 256))
