@@ -55,6 +55,8 @@ def parse():
                     help="print a markdown summary of rocprofv3 output folders (TRACE FETCH WRITE CFETCH CWRITE "
                          "[SQ]) and exit")
     ap.add_argument("--commands", nargs="+", default=None, help="the profiling commands, for the summary")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TITLE", "TRACE", "COMMAND"),
+                    help="print a markdown table of kernel durations from one rocprofv3 kernel-trace folder and exit")
     return ap.parse_args()
 
 
@@ -149,6 +151,26 @@ def copy_probe() -> None:
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_per_dispatch": n * 4, "dispatches": 5}), flush=True)
+
+
+def summarize_trace(title: str, trace_dir: str, command: str) -> str:
+    """Markdown table of the library's kernel durations in one kernel-trace folder."""
+    import csv
+    import glob
+    hits = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not hits:
+        raise FileNotFoundError(f"kernel_stats.csv under {trace_dir}")
+
+    def short(k):
+        return k.replace("(anonymous namespace)::", "").replace("frnn::", "").replace("void ", "").split("(")[0]
+
+    out = [f"# rocprofv3 summary: {title}", "", f"kernel sources sha256/16: {kernel_source_digest()}", "",
+           f"command: `{command}`", "", "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for r in csv.DictReader(open(hits[0])):
+        if short(r["Name"]).startswith("k_"):
+            out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                       f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+    return "\n".join(out + [""])
 
 
 # MI355X issue model: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies a
@@ -453,6 +475,10 @@ def labeling_bench(spec, X, pts, steps: int, warmup: int, log, cpu: bool) -> dic
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        title, trace, command = args.summarize_trace
+        print(summarize_trace(title, trace, command))
+        return
     if args.summarize:
         if len(args.summarize) not in (5, 6):
             raise SystemExit("--summarize takes TRACE FETCH WRITE CFETCH CWRITE [SQ]")
