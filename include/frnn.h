@@ -65,7 +65,8 @@ typedef struct frnn_config {
                           (0 means 1).  Neighbours are searched cell_div cells away. */
     int32_t grid_mult; /* search workgroups as a multiple of those that fit on the GPU at
                           once: 1, 2, 4 or 8; 0 (default) chooses from the rows per wave
-                          (1 for few rows, up to 4 for many) */
+                          (1 up to 128 rows per resident wave, up to 4 beyond).  With 1,
+                          waves order their issue priority by progress. */
     int32_t flags;     /* FRNN_FLAG_* bits */
 } frnn_config;
 
