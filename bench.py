@@ -55,6 +55,9 @@ def parse():
                     help="print a markdown summary of rocprofv3 output folders (TRACE FETCH WRITE CFETCH CWRITE "
                          "[SQ]) and exit")
     ap.add_argument("--commands", nargs="+", default=None, help="the profiling commands, for the summary")
+    ap.add_argument("--batch-only", type=int, default=0, metavar="CALLS",
+                    help="build the 64-event batch CALLS times with binned coordinates 4, 5, 7 and the "
+                         "default grid (a run to profile) and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TITLE", "TRACE", "COMMAND"),
                     help="print a markdown table of kernel durations from one rocprofv3 kernel-trace folder and exit")
     return ap.parse_args()
@@ -151,6 +154,23 @@ def copy_probe() -> None:
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_per_dispatch": n * 4, "dispatches": 5}), flush=True)
+
+
+def batch_only(calls: int) -> None:
+    """The benchmark's 64-event batch built `calls` times with one fixed config."""
+    import numpy as np
+    import torch
+
+    from paper_2202_06929_amd import events, frnn
+    sizes = events.batched_sizes()
+    evs = [events.generate(events.batched_spec(n, 100 + k))[0] for k, n in enumerate(sizes)]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pts = torch.from_numpy(np.concatenate(evs)).to("cuda:0")
+    cfg = frnn.Config(dims=(4, 5, 7))
+    for k in range(calls):
+        edges, eo = frnn.build_batch(pts, offsets, 0.1, 256, cfg)
+    torch.cuda.synchronize()
+    print(json.dumps({"batch_calls": calls, "rows": int(offsets[-1]), "edges": int(eo[-1])}), flush=True)
 
 
 def summarize_trace(title: str, trace_dir: str, command: str) -> str:
@@ -475,6 +495,9 @@ def labeling_bench(spec, X, pts, steps: int, warmup: int, log, cpu: bool) -> dic
 
 def main():
     args = parse()
+    if args.batch_only:
+        batch_only(args.batch_only)
+        return
     if args.summarize_trace:
         title, trace, command = args.summarize_trace
         print(summarize_trace(title, trace, command))
