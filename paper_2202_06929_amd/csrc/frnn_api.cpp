@@ -126,8 +126,7 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.sums_kept2 = cv.take<unsigned long long>(groups_kept);
     // One padding row after the last: the search requests the row after each query.
     ws.sorted = cv.take<float>(static_cast<size_t>(rows + 1) * dpad);
-    ws.sorted_id = cv.take<unsigned int>(rows);
-    ws.sorted_key = cv.take<unsigned int>(rows);
+    ws.sorted_id = cv.take<unsigned int>(2 * rows);
     ws.kept = cv.take<unsigned int>(rows);
     ws.tpos = cv.take<unsigned long long>(rows);
     ws.heavy = cv.take<HeavyEntry>(rows);

@@ -106,8 +106,7 @@ struct Workspace {
     unsigned long long *sums_kept;   // [tiles of kPlaceTile rows] per-tile kept totals
     unsigned long long *sums_kept2;  // [groups of kKeptGroup tiles] per-group kept totals
     float *sorted;              // [rows, dpad] points in cell order, zero-padded rows
-    unsigned int *sorted_id;    // [rows] original row of each sorted row
-    unsigned int *sorted_key;   // [rows] cell key of each sorted row
+    unsigned int *sorted_id;    // [2 rows] per sorted row: its original row, then its cell key
     unsigned int *kept;         // [rows] neighbours kept per original row
     unsigned long long *tpos;   // [rows] where each query's list sits in `temp`
     HeavyEntry *heavy;          // [rows]

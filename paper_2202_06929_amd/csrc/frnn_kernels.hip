@@ -448,8 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
                                                     const unsigned int *__restrict__ cell_start,
                                                     const Counters *__restrict__ ctr,
                                                     float *__restrict__ sorted,
-                                                    unsigned int *__restrict__ sorted_id,
-                                                    unsigned int *__restrict__ sorted_key) {
+                                                    unsigned int *__restrict__ sorted_id) {
     if (ctr->abort) return;
     const EventDesc E = ev[blockIdx.y];
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < E.n; i += gridDim.x * kBlock) {
@@ -477,8 +476,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
 #pragma unroll
         for (int k = 0; k < DP / 4; ++k)
             out[k] = make_float4(row[4 * k], row[4 * k + 1], row[4 * k + 2], row[4 * k + 3]);
-        sorted_id[slot] = static_cast<unsigned int>(gi);
-        sorted_key[slot] = ck;
+        // The original row and the cell key of a sorted row sit side by side, so the
+        // scattered write is one 8-byte store instead of two 4-byte ones.
+        reinterpret_cast<uint2 *>(sorted_id)[slot] = make_uint2(static_cast<unsigned int>(gi), ck);
     }
 }
 
@@ -539,7 +539,7 @@ constexpr int kSearchWaves = DP <= 8 ? 8 : 1;
 template <int DP, bool SEL>
 __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float *__restrict__ sorted,
                                                    const unsigned int *__restrict__ sorted_id,
-                                                   const unsigned int *__restrict__ sorted_key, unsigned int q_base,
+                                                   unsigned int q_base,
                                                    unsigned int q_rem,
                                                    const EventDesc *__restrict__ ev, int n_events,
                                                    const unsigned int *__restrict__ cell_start,
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned int cell0 = 0;
     int nruns = 1;
     for (unsigned int qa = q_lo; qa < q_hi;) {
-        const unsigned int cell = uniform(sorted_key[qa]);
+        const unsigned int cell = uniform(sorted_id[2u * qa + 1u]);
         const unsigned int qs = qa;
         const unsigned int qe = min(uniform(cell_start[cell + 1]), q_hi);
         qa = qe;
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         cn[3] = v.w;
                     } else {
                         load_row<DP>(sorted, sn, cn);
-                        jn = sorted_id[sn];
+                        jn = sorted_id[2u * sn];
                     }
                     // Lanes past the last candidate fail every first-stage test.
                     if (mm >= M) cn[0] = INFINITY;
@@ -700,7 +700,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     float cc[DP];
 #pragma unroll
                     for (int k = kLead; k < DP; ++k) cc[k] = crow[k];
-                    const unsigned int j2 = sorted_id[s2];
+                    const unsigned int j2 = sorted_id[2u * s2];
                     const float D = add_terms<kLead, DP, DP>(a3, cc, sorted + static_cast<size_t>(q0 + q) * DP);
                     keep(act && D < r2 && s2 != q0 + q, q, j2, D);
                     wave_lds_sync();
@@ -790,7 +790,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                   (SEL || cnt <= static_cast<unsigned int>(K));
                 if (lane < Qn) {
                     const unsigned int slot = q0 + lane;
-                    const unsigned int i = sorted_id[slot];
+                    const unsigned int i = sorted_id[2u * slot];
                     kept[i] = min(cnt, static_cast<unsigned int>(K));
                     if (cnt > static_cast<unsigned int>(K)) ++capped;
                     if (fits) {
@@ -975,7 +975,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
             load_row<DP>(sorted, s, c);
             const float D = sq_dist<DP>(c, q);
             ok = (D < r2) && (s != he.slot);
-            return (static_cast<unsigned long long>(__float_as_uint(D)) << 32) | sorted_id[s];
+            return (static_cast<unsigned long long>(__float_as_uint(D)) << 32) | sorted_id[2u * s];
         };
 
         unsigned int n_out;
@@ -1047,7 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
         }
         if (threadIdx.x == 0) {
             base_s = atomicAdd(&ctr->heavy_top, static_cast<unsigned long long>(n_out));
-            tpos[sorted_id[he.slot]] = heavy_base + base_s;
+            tpos[sorted_id[2u * he.slot]] = heavy_base + base_s;
         }
         __syncthreads();
         const unsigned long long base = base_s;
@@ -1234,18 +1234,18 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     const long long nb = (static_cast<long long>(a.max_n) + kBlock - 1) / kBlock;
     const int gs = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
     hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, ws.key,
-                       ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id, ws.sorted_key);
+                       ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id);
     mark(4);
     const unsigned int sq_base = static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves));
     const unsigned int sq_rem = static_cast<unsigned int>(rows % (static_cast<long long>(a.search_blocks) * kWaves));
     if (a.K < kListCap)
         hipLaunchKernelGGL((k_search<DP, true>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
-                           ws.sorted_id, ws.sorted_key, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
+                           ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
                            a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
                            a.search_prio);
     else
         hipLaunchKernelGGL((k_search<DP, false>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
-                           ws.sorted_id, ws.sorted_key, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
+                           ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
                            a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
                            a.search_prio);
     mark(5);
