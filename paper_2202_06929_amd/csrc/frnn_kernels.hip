@@ -18,9 +18,9 @@
 //   k_heavy       kept totals per tile and per group of tiles; queries whose list
 //                 is longer than the search keeps, or longer than K: the K smallest
 //                 by (D, j) found by an MSB-first radix select
-//   k_place       output offsets from the totals and a block scan; each list entry
-//                 ranked within its list and the edges written to their
-//                 (i asc, j asc) positions
+//   k_place       output offsets from the totals and a block scan; each short list
+//                 sorted by its query's thread and staged in LDS; the edges written
+//                 to their (i asc, j asc) positions with coalesced stores
 //
 // Distances follow one fixed order with every product and sum rounded on its
 // own: this file is compiled with -ffp-contract=off and the pragma below.
@@ -1064,10 +1064,10 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
 // kKeptGroup tiles, then the tiles of its own group); a block scan of its kept
 // counts gives each query's offset.  Output positions are then mapped to their
 // query through an owner table in LDS, a window at a time, so that consecutive
-// threads handle consecutive int64 positions.  Lists in the fixed kListCap-slot
-// places come from the search in the order their hits were found: a thread reads
-// its entry's whole list (four 16-byte loads) and writes the entry at its rank by
-// neighbour id.  Long lists come sorted from the long-list kernel.  Indices are
+// threads write consecutive int64 positions.  Lists in the fixed kListCap-slot
+// places come from the search in the order their hits were found: each query's
+// thread sorts its list in registers and stages it in LDS first.  Long lists come
+// sorted from the long-list kernel.  Indices are
 // made local to each query's event.  Block 0 writes the report and the status; the
 // block holding an event's first row writes its edge offset.
 __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const EventDesc *__restrict__ ev,
@@ -1090,6 +1090,7 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     __shared__ unsigned long long tp[kPlaceTile];
     __shared__ unsigned int base_row[kPlaceTile];
     __shared__ unsigned char owner[kOwnerWindow];
+    __shared__ __align__(16) unsigned int staged[kPlaceTile * kListCap];  // sorted fixed-place lists
     __shared__ unsigned long long scratch[kWaves];
     const bool abort = ctr->abort != 0;
     const int b = static_cast<int>(blockIdx.x);
@@ -1175,6 +1176,48 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     if (pre + total > cap) return;  // cannot happen when E <= cap; never write past the outputs
     // End of the fixed list places; long lists live after it.
     const unsigned long long fixed_end = static_cast<unsigned long long>(rows) * kListCap;
+    // Lists in the fixed places come from the search in the order their hits were
+    // found: the query's thread sorts its list (a bitonic network over 16 slots, the
+    // unused ones holding the largest value) and stages it in LDS.
+    if (q < cnt && kq > 0u) {
+        const unsigned long long t0 = tpos[i0 + q];
+        if (t0 < fixed_end && t0 + kListCap <= temp_len) {
+            const uint4 *l4 = reinterpret_cast<const uint4 *>(temp + t0);
+            unsigned int v[kListCap];
+#pragma unroll
+            for (int c = 0; c < kListCap / 4; ++c) {
+                const uint4 w = l4[c];
+                v[4 * c] = w.x;
+                v[4 * c + 1] = w.y;
+                v[4 * c + 2] = w.z;
+                v[4 * c + 3] = w.w;
+            }
+#pragma unroll
+            for (int u = 0; u < kListCap; ++u) v[u] = static_cast<unsigned int>(u) < kq ? v[u] : 0xffffffffu;
+#pragma unroll
+            for (int k = 2; k <= kListCap; k <<= 1) {
+#pragma unroll
+                for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+                    for (int u = 0; u < kListCap; ++u) {
+                        const int l = u ^ j;
+                        if (l > u) {
+                            const unsigned int lo = v[u] < v[l] ? v[u] : v[l];
+                            const unsigned int hi = v[u] < v[l] ? v[l] : v[u];
+                            const bool up = (u & k) == 0;
+                            v[u] = up ? lo : hi;
+                            v[l] = up ? hi : lo;
+                        }
+                    }
+                }
+            }
+            uint4 *st = reinterpret_cast<uint4 *>(staged + q * kListCap);
+#pragma unroll
+            for (int c = 0; c < kListCap / 4; ++c)
+                st[c] = make_uint4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+        }
+    }
+    __syncthreads();
     for (unsigned int w0 = 0; w0 < total; w0 += kOwnerWindow) {
         const unsigned int wend = total - w0 < kOwnerWindow ? total - w0 : kOwnerWindow;
         if (q < cnt) {
@@ -1187,38 +1230,17 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
             const int r = owner[p];
             const unsigned int pos = w0 + p;
             const unsigned int k = pos - o[r];
-            const unsigned int len = o[r + 1] - o[r];
             const unsigned long long t0 = tp[r];
             src[static_cast<long long>(pre) + pos] = i0 + r - base_row[r];
             // The list positions come from the search; the bounds only keep a
             // corrupted position from reading outside the workspace.
-            unsigned int rank = k;
             long long v = -1ll;
             if (t0 < fixed_end) {
-                if (t0 + kListCap <= temp_len) {
-                    const uint4 *l4 = reinterpret_cast<const uint4 *>(temp + t0);
-                    unsigned int l[kListCap];
-#pragma unroll
-                    for (int c = 0; c < kListCap / 4; ++c) {
-                        const uint4 w = l4[c];
-                        l[4 * c] = w.x;
-                        l[4 * c + 1] = w.y;
-                        l[4 * c + 2] = w.z;
-                        l[4 * c + 3] = w.w;
-                    }
-                    unsigned int x = l[0];
-#pragma unroll
-                    for (int u = 1; u < kListCap; ++u) x = k == static_cast<unsigned int>(u) ? l[u] : x;
-                    rank = 0;
-#pragma unroll
-                    for (int u = 0; u < kListCap; ++u)
-                        rank += (static_cast<unsigned int>(u) < len && l[u] < x) ? 1u : 0u;
-                    v = static_cast<long long>(x) - base_row[r];
-                }
+                if (t0 + kListCap <= temp_len) v = static_cast<long long>(staged[r * kListCap + k]) - base_row[r];
             } else if (t0 + k < temp_len) {
                 v = static_cast<long long>(temp[t0 + k]) - base_row[r];
             }
-            dst[static_cast<long long>(pre) + o[r] + rank] = v;
+            dst[static_cast<long long>(pre) + pos] = v;
         }
         __syncthreads();
     }
