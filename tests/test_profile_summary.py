@@ -74,3 +74,12 @@ def test_stored_figures_follow_the_source_digest(dirs, tmp_path, monkeypatch):
     path.write_text(text.replace(bench.kernel_source_digest(), "0000000000000000"))
     assert bench.stored_traffic("k_search<8, false>") is None
     assert bench.stored_valu("k_search<8, false>") is None
+
+
+def test_trace_only_summary(dirs):
+    text = bench.summarize_trace("a workload", dirs["trace"], "the command")
+    assert text.startswith("# rocprofv3 summary: a workload")
+    assert f"kernel sources sha256/16: {bench.kernel_source_digest()}" in text
+    assert "command: `the command`" in text
+    assert "| k_search<8, false> | 10 | 50.00 | 40.00 | 60.00 |" in text
+    assert "copyBuffer" not in text  # only the library's kernels are listed
