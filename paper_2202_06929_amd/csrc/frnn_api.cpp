@@ -17,9 +17,13 @@
 
 namespace frnn {
 
+// Cell capacity of an event: n / 2 cells, at least 2^15 and at most 2^22.  The grid
+// plan coarsens its cells until the grid fits (a speed choice only: the search is
+// exact for any grid); a workload's grid of r-sized cells is usually far smaller,
+// and every cell of the capacity is cleared and scanned per call.
 int64_t cells_max_for(int64_t n) {
     if (n <= 0) return 1;
-    int64_t c = 2 * n;
+    int64_t c = n / 2;
     if (c < (int64_t{1} << 15)) c = int64_t{1} << 15;
     if (c > (int64_t{1} << 22)) c = int64_t{1} << 22;
     return c;
