@@ -551,12 +551,15 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                                    Counters *__restrict__ ctr,
                                                    unsigned long long *__restrict__ tested_out,
                                                    unsigned int *__restrict__ capped_out, int prio) {
-    __shared__ __align__(16) unsigned int lst_all[kWaves][kQTile * kListCap];
-    __shared__ unsigned int lstd_all[SEL ? kWaves : 1][SEL ? kQTile * kListCap : 1];  // D bits of each hit
-    __shared__ unsigned long long thr_all[SEL ? kWaves : 1][SEL ? kQTile : 1];       // K-th smallest (D, j) key
-    __shared__ unsigned int pre_all[kWaves][kQTile + 1];
-    __shared__ unsigned int cnt_all[kWaves][kQTile];
-    __shared__ unsigned int qcnt_all[kWaves][kQTile];
+    // Queries per tile: 16 when the lists also hold distances (their LDS would
+    // otherwise cost occupancy), else kQTile.
+    constexpr int kQT = SEL ? 16 : kQTile;
+    __shared__ __align__(16) unsigned int lst_all[kWaves][kQT * kListCap];
+    __shared__ unsigned int lstd_all[SEL ? kWaves : 1][SEL ? kQT * kListCap : 1];  // D bits of each hit
+    __shared__ unsigned long long thr_all[SEL ? kWaves : 1][SEL ? kQT : 1];       // K-th smallest (D, j) key
+    __shared__ unsigned int pre_all[kWaves][kQT + 1];
+    __shared__ unsigned int cnt_all[kWaves][kQT];
+    __shared__ unsigned int qcnt_all[kWaves][kQT];
     // Row-addressed entries: q << 32 | candidate row, with the partial sum in racc;
     // lane-addressed entries: (q << 6 | lane) << 32 | bits of the partial sum.
     __shared__ unsigned long long ring_all[kWaves][kRing];
@@ -619,8 +622,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
             }
             unsigned int start, pre;
             const unsigned int M = wave_runs(cell - cell0, cell0, P, cell_start, start, pre);
-            for (unsigned int q0 = qs; q0 < qe; q0 += kQTile) {
-                const int Qn = static_cast<int>(uniform(min(static_cast<unsigned int>(kQTile), qe - q0)));
+            for (unsigned int q0 = qs; q0 < qe; q0 += kQT) {
+                const int Qn = static_cast<int>(uniform(min(static_cast<unsigned int>(kQT), qe - q0)));
                 if (prio) {
                     // A SIMD issues the oldest ready wave first, so with every workgroup
                     // resident from the start the waves dispatched last finish last and
@@ -635,7 +638,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     else if (4u * left > share) __builtin_amdgcn_s_setprio(1);
                     else __builtin_amdgcn_s_setprio(0);
                 }
-                if (lane < kQTile) qcnt[lane] = 0u;
+                if (lane < kQT) qcnt[lane] = 0u;
                 // Candidate rows are fetched one chunk ahead so that their latency
                 // overlaps the tests of the current chunk (with row-addressed ring entries
                 // only the leading coordinates, one 16-byte load).  Idle lanes read row 0
