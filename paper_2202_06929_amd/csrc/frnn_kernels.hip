@@ -529,10 +529,12 @@ __device__ __forceinline__ unsigned int wave_runs(unsigned int cell, unsigned in
 
 // ------------------------------------------------------------------ search
 
-// Waves per SIMD the search asks the register allocator for: narrow rows fit in
-// 64 registers (8 waves); wider rows keep the compiler's choice (no spills).
+// Waves per SIMD the search asks the register allocator for: rows of up to 8
+// floats fit in 64 registers (8 waves); 12-float rows spill a few registers at 8
+// waves, which still runs faster than 6 waves without spills; wider rows keep
+// the compiler's choice (no spills).
 template <int DP>
-constexpr int kSearchWaves = DP <= 8 ? 8 : 1;
+constexpr int kSearchWaves = DP <= 12 ? 8 : 1;
 
 // SEL: the cap K is below kListCap, so a list that fits may still need the K
 // nearest of its hits: the lists then also hold each hit's distance.
