@@ -582,8 +582,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     const unsigned int total_waves = gridDim.x * kWaves;
     // Terms before the first exact rejection test: two for rows of up to 8 floats
     // (their three-term test rejects few more pairs than two terms do, and the
-    // first stage runs for every query and candidate), three for wider rows.
-    constexpr int kLead = DP <= 8 ? 2 : 3;
+    // first stage runs for every query and candidate), four for 12-float rows
+    // (fewer survivors for the lane exchange of the second stage), three for
+    // wider rows.
+    constexpr int kLead = DP <= 8 ? 2 : (DP <= 12 ? 4 : 3);
     // Row-addressed ring entries (the entry names the candidate's sorted row and the
     // remaining coordinates are loaded when the entry is finished) for rows of up to
     // 8 floats; wider rows exchange the candidate's coordinates between lanes instead.
