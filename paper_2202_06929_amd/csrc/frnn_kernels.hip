@@ -12,8 +12,8 @@
 //                 cell's queries against the (2R+1)^2 contiguous x-runs of
 //                 neighbouring cells; each lane holds one candidate (its leading
 //                 coordinates, or its whole row for rows wider than 8 floats), query
-//                 rows are wave-uniform; an exact early exit after the first two or
-//                 three terms of the distance sum; ballots queue the survivors, whose
+//                 rows are wave-uniform; an exact early exit after the first two to
+//                 four terms of the distance sum; ballots queue the survivors, whose
 //                 sums are finished 64 at a time; each list is stored as found
 //   k_heavy       kept totals per tile and per group of tiles; queries whose list
 //                 is longer than the search keeps, or longer than K: the K smallest
