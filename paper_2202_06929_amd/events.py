@@ -209,6 +209,27 @@ def stress_cases(seed: int = 11) -> list[StressCase]:
     return out
 
 
+def dense_cells(d: int, seed: int = 23) -> np.ndarray:
+    """2,600 float32 points in d dimensions for radius 0.1, with crowded cells.
+
+    A clump of 300 points (sigma 0.01) and 200 points sharing their binned
+    coordinates 0-2 and d-3..d-1 (one cell) give cells of hundreds of queries, so
+    the search runs many query tiles per cell, ending in a partial one; three
+    clumps of 300 with sigma 0.1 f / sqrt(d), f = 1.0, 1.2, 1.5, give hundreds of
+    queries with 5 to 16 neighbours at every d; 1,200 uniform points in [-1, 1]^d
+    surround them.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    slab = rng.uniform(-1, 1, size=(200, d))
+    slab[:, :3] = 0.3
+    slab[:, d - 3:] = -0.3
+    parts = [_clump(rng, 300, d, 0.01), slab]
+    parts += [_clump(rng, 300, d, 0.1 * f / np.sqrt(d)) for f in (1.0, 1.2, 1.5)]
+    parts.append(rng.uniform(-1, 1, size=(1200, d)))
+    X = np.concatenate(parts)
+    return X[rng.permutation(len(X))].astype(np.float32)
+
+
 def dyadic_event(n: int, d: int, seed: int, step_log2: int = 6,
                  n_clusters: int = 40, sigma: float = 0.05) -> tuple[np.ndarray, np.ndarray]:
     """Clustered points snapped to multiples of 2^-step_log2 in [-1, 1].

@@ -271,6 +271,18 @@ def test_small_caps_keep_the_nearest(K):
     assert_same(gpu_edges(X, spec.r, K), oracle.frnn_grid(X, spec.r, K))
 
 
+@pytest.mark.parametrize("d", [3, 8, 12, 16])
+@pytest.mark.parametrize("K", [1, 4, 15])
+def test_small_caps_on_dense_cells(d, K):
+    """Caps below the list size where cells hold many queries: several query tiles
+    per cell with a partial last one, at each row width of the capped search."""
+    X = events.dense_cells(d)
+    log(f"small cap K={K} on dense cells d={d}")
+    want = oracle.frnn_grid(X, 0.1, K)
+    assert_same(gpu_edges(X, 0.1, K), want)
+    assert_same(gpu_edges(X, 0.1, K, config=frnn.Config(dims=(0, 1, 2))), want)
+
+
 def test_nearest_eight_on_the_single_event():
     """The kNN-then-radius workload: K = 8 binds for about half the queries."""
     spec = events.KNN
