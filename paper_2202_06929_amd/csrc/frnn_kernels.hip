@@ -530,11 +530,11 @@ __device__ __forceinline__ unsigned int wave_runs(unsigned int cell, unsigned in
 // ------------------------------------------------------------------ search
 
 // Waves per SIMD the search asks the register allocator for: rows of up to 8
-// floats fit in 64 registers (8 waves); 12-float rows spill a few registers at 8
-// waves, which still runs faster than 6 waves without spills; wider rows keep
-// the compiler's choice (no spills).
+// floats fit in 64 registers (8 waves); 12-float rows take 72 registers (7
+// waves; the compiler's own choice ran 6 waves, and 8 waves spill); wider rows
+// keep the compiler's choice (no spills).
 template <int DP>
-constexpr int kSearchWaves = DP <= 12 ? 8 : 1;
+constexpr int kSearchWaves = DP <= 8 ? 8 : (DP <= 12 ? 7 : 1);
 
 // SEL: the cap K is below kListCap, so a list that fits may still need the K
 // nearest of its hits: the lists then also hold each hit's distance.
