@@ -27,12 +27,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published peaks.  Plain FP32 VALU lane-ops: 256 CUs x 64 lanes x 2.4 GHz
-# = 39.3 T/s (the 157.3 TFLOP/s vector figure counts fused multiply-add as two
-# and packed FP32 as two lanes; this path may use neither).
+# MI355X published peaks: HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s (256 CUs x
+# 2.4 GHz x 256 FLOP per CU and cycle, which counts a fused multiply-add as two
+# operations and packed FP32 as two lanes).  The distance test may use neither
+# (every product and sum is rounded on its own), so its own issue ceiling is one
+# FP32 operation per lane and cycle: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T/s,
+# reported beside the published figure, never in its place.
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+PLAIN_LANE_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+PATH_HBM_TARGET = 0.5
 METRIC = "events/s and edges/s at 120k hits; p50/p99 per-event latency; HBM GB/s vs peak"
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+LATENCY_SAMPLES = 200
 
 
 def log(msg: str) -> None:
@@ -76,21 +82,71 @@ def path_bytes(n: int, d: int, E: int) -> int:
     return 5 * n * d * 4 + 40 * n + 16 * E
 
 
-def cpu_baseline(spec, X, budget_s: float = 10.0) -> dict:
-    """The CPU oracle (plain C grid route, one thread) on the same event, repeated
-    until about budget_s seconds of CPU work have run (at least 3 runs)."""
+def host_threads() -> int:
+    """Host threads this process may use (its CPU affinity), at most 16: the GPU
+    box's share of host cores for one GPU."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(spec, X, single_s: float = 6.0, multi_s: float = 1.5) -> dict:
+    """The CPU oracle (plain C grid route, unchanged) on the same event.
+
+    Two legs: one host thread, repeated for about single_s seconds (at least 3
+    runs); then every usable host thread (host_threads()) each building the event
+    over and over for about multi_s seconds of wall time, events being independent.
+    `value` is the all-threads rate with `cores` the threads used; the one-thread
+    rate is reported beside it."""
+    import threading
+
     from oracle import oracle
     oracle.load()
     runs = []
     t0 = time.perf_counter()
-    while len(runs) < 3 or time.perf_counter() - t0 < budget_s:
+    while len(runs) < 3 or time.perf_counter() - t0 < single_s:
         t = time.perf_counter()
         oracle.frnn_grid(X, spec.r, spec.K)
         runs.append(time.perf_counter() - t)
-    total = sum(runs)
-    return {"value": len(runs) / total, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"the same event (n={spec.n}, d={spec.d}) built {len(runs)} times by the oracle's grid "
-                      f"route on one host thread, {total:.1f} s in total (median {statistics.median(runs):.3f} s)"}
+    one = len(runs) / sum(runs)
+
+    threads = host_threads()
+    counts = [0] * threads
+    stop = time.perf_counter() + multi_s
+
+    def work(k):
+        while time.perf_counter() < stop or counts[k] == 0:
+            oracle.frnn_grid(X, spec.r, spec.K)  # the C call runs outside the interpreter lock
+            counts[k] += 1
+
+    pool = [threading.Thread(target=work, args=(k,)) for k in range(threads)]
+    t = time.perf_counter()
+    for th in pool:
+        th.start()
+    for th in pool:
+        th.join()
+    wall = time.perf_counter() - t
+    many = sum(counts) / wall
+    return {"value": many, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"the same event (n={spec.n}, d={spec.d}) built by the oracle's grid route: {sum(counts)} "
+                      f"builds on {threads} host threads in {wall:.1f} s of wall time (one event per thread at a "
+                      f"time); and {len(runs)} builds on one thread, {sum(runs):.1f} s (median "
+                      f"{statistics.median(runs):.3f} s)",
+            "single_core": {"value": one, "unit": "events/s", "cores": 1},
+            "host_cpu": host_cpu(), "host_cpus_visible": os.cpu_count()}
 
 
 def kernel_source_digest() -> str:
@@ -141,6 +197,46 @@ def stored_valu(kernel: str) -> float | None:
         if line.startswith(f"valu {kernel} issue utilisation:"):
             value = float(line.split(":", 1)[1].strip())
     return value if digest == kernel_source_digest() else None
+
+
+def identity() -> dict:
+    """GPU, ROCm and host of this run."""
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    rocm = None
+    for f in ("/opt/rocm/.info/version", "/opt/rocm/.info/version-dev"):
+        try:
+            with open(f) as fh:
+                rocm = fh.read().strip()
+                break
+        except OSError:
+            pass
+    return {"gpu": props.name, "arch": getattr(props, "gcnArchName", "?"), "cus": props.multi_processor_count,
+            "hbm_gib": round(props.total_memory / 2 ** 30, 1), "rocm": rocm, "hip_runtime": torch.version.hip,
+            "torch": torch.__version__, "host_cpu": host_cpu(), "host_cpus_visible": os.cpu_count()}
+
+
+def copy_bandwidth(gib: float = 1.0, reps: int = 10) -> dict:
+    """Device-to-device copy of `gib` GiB: read + write bytes over the best HIP-event time."""
+    import torch
+    n = int(gib * 2 ** 30) // 4
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        b.copy_(a)
+        e.record()
+        e.synchronize()
+        best = min(best, s.elapsed_time(e) * 1e-3)
+    gbs = 2 * n * 4 / best / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"gbs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "bytes_per_copy": 2 * n * 4,
+            "how": f"torch copy of {gib:g} GiB on the device, best of {reps} HIP-event timings"}
 
 
 def copy_probe() -> None:
@@ -375,13 +471,19 @@ def batched_bench(steps: int, warmup: int, log) -> dict:
             "tune": treport.get("all")}
 
 
-def served_bench(log, n_events: int = 300, load: float = 1.0) -> dict:
+SERVED_LOADS = (0.5, 0.8, 1.0, 1.2, 2.0)
+
+
+def served_bench(log, n_arrivals: int = 1000, n_distinct: int = 250, loads=SERVED_LOADS) -> dict:
     """Poisson arrivals of events with log-uniform hit counts in [10k, 300k].
 
-    The arrival rate is `load` times the plain loop's measured capacity (events/s
-    of one synchronous call per event).  The same trace runs through the plain loop
-    and through the continuous-batching server; a sample of served results is
-    checked byte-for-byte against the same event built alone.
+    n_distinct events are drawn once (sizes log-uniform in [10k, 300k]) and request
+    k carries event k mod n_distinct.  The plain loop's capacity (events/s of one
+    synchronous call per event, back to back) is measured first; then, for every
+    offered load in `loads` (a multiple of that capacity), the same trace of
+    n_arrivals Poisson arrivals runs through the plain loop and through the
+    continuous-batching server, and every served result is compared byte for byte
+    with the plain loop's result for the same request.
     """
     import numpy as np
     import torch
@@ -389,51 +491,58 @@ def served_bench(log, n_events: int = 300, load: float = 1.0) -> dict:
     from paper_2202_06929_amd import events, frnn, serve
 
     r, K, d = 0.1, 256, 8
-    base = events.served_trace(n_events, rate_hz=1.0)
-    pts = [events.generate(events.batched_spec(n, 10_000 + k))[0] for k, (_, n) in enumerate(base)]
+    base = events.served_trace(n_arrivals, rate_hz=1.0)
+    pts = [events.generate(events.batched_spec(n, 10_000 + k))[0] for k, (_, n) in enumerate(base[:n_distinct])]
     dev = torch.device("cuda:0")
     dev_pts = [torch.from_numpy(x).to(dev) for x in pts]
+    ev_of = [k % n_distinct for k in range(n_arrivals)]
 
     def build(req):
-        return frnn.build(dev_pts[req.rid], r, K)
+        return frnn.build(req.points, r, K)
 
     # Plain-loop capacity on these events (warm, back to back).
-    for k in range(5):
+    for k in range(10):
         build(serve.Request(rid=k, arrival=0.0, points=dev_pts[k]))
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for k in range(n_events):
-        build(serve.Request(rid=k, arrival=0.0, points=dev_pts[k]))
+    for k in range(n_arrivals):
+        build(serve.Request(rid=k, arrival=0.0, points=dev_pts[ev_of[k]]))
     torch.cuda.synchronize()
-    capacity = n_events / (time.perf_counter() - t)
-    rate = load * capacity
-    arrivals = [a / rate for a, _ in base]  # the unit-rate trace scaled to the target rate
-
-    def trace():
-        return [serve.Request(rid=k, arrival=arrivals[k], points=dev_pts[k]) for k in range(n_events)]
+    capacity = n_arrivals / (time.perf_counter() - t)
 
     def idle(until):
         while time.perf_counter() < until:
             pass
 
-    plain_trace = trace()
-    plain = serve.plain_loop(plain_trace, build, idle=idle)
     ex = serve.GpuExecutor(r, K, d, n_streams=3)
-    warm = serve.Server(ex, hbm_budget=64 << 30, max_batch=64, idle=idle)
-    warm.run(trace()[:20])
-    served_trace = trace()
-    srv = serve.Server(ex, hbm_budget=64 << 30, max_batch=64, idle=idle)
-    served = srv.run(served_trace)
-    for k in range(0, n_events, max(1, n_events // 10)):
-        a = served_trace[k].edges
-        b = plain_trace[k].edges
-        assert served_trace[k].status == serve.OK and torch.equal(a.cpu(), b.cpu()), f"served event {k} differs"
-    log(f"served: plain p50 {plain.p50_ms:.2f} p99 {plain.p99_ms:.2f} ms, {plain.events_per_s:.0f}/s; "
-        f"server p50 {served.p50_ms:.2f} p99 {served.p99_ms:.2f} ms, {served.events_per_s:.0f}/s")
-    return {"workload": f"served: {n_events} Poisson arrivals at {rate:.0f}/s ({load:.2f} x plain-loop capacity), "
-                        "hits log-uniform in [10000, 300000], 8-D float32, r=0.1, K=256, HBM budget 64 GB",
-            "plain_capacity_events_per_s": capacity, "plain": plain.as_dict(), "server": served.as_dict(),
-            "parity": "sampled served events identical to the same event alone"}
+    warm = [serve.Request(rid=k, arrival=0.0, points=dev_pts[k]) for k in range(40)]
+    serve.Server(ex, hbm_budget=64 << 30, max_batch=64, idle=idle).run(warm)
+    rows = []
+    for load in loads:
+        rate = load * capacity
+        arrivals = [a / rate for a, _ in base]  # the unit-rate trace scaled to the offered rate
+
+        def trace():
+            return [serve.Request(rid=k, arrival=arrivals[k], points=dev_pts[ev_of[k]]) for k in range(n_arrivals)]
+
+        plain_trace = trace()
+        plain = serve.plain_loop(plain_trace, build, idle=idle)
+        served_trace = trace()
+        served = serve.Server(ex, hbm_budget=64 << 30, max_batch=64, idle=idle).run(served_trace)
+        same = all(q.status == serve.OK and torch.equal(q.edges, p.edges) for q, p in zip(served_trace, plain_trace))
+        if not same:
+            raise RuntimeError(f"served results differ from the plain loop's at load {load}")
+        log(f"served x{load}: plain p50 {plain.p50_ms:.2f} p99 {plain.p99_ms:.2f} ms, {plain.events_per_s:.0f}/s; "
+            f"server p50 {served.p50_ms:.2f} p99 {served.p99_ms:.2f} ms, {served.events_per_s:.0f}/s, "
+            f"mean batch {served.mean_batch:.1f}")
+        rows.append({"load": load, "offered_events_per_s": rate, "plain": plain.as_dict(), "server": served.as_dict(),
+                     "server_vs_plain_events_per_s": served.events_per_s / plain.events_per_s,
+                     "server_vs_plain_p99": served.p99_ms / plain.p99_ms})
+    return {"workload": f"served: {n_arrivals} Poisson arrivals per load, each carrying one of {n_distinct} events "
+                        "with hits log-uniform in [10000, 300000] (8-D float32, r=0.1, K=256), HBM budget 64 GB, "
+                        "3 streams, batches of at most 64",
+            "plain_capacity_events_per_s": capacity, "loads": rows,
+            "parity": "every served result identical to the plain loop's result for the same request"}
 
 
 def labeling_bench(spec, X, pts, steps: int, warmup: int, log, cpu: bool) -> dict:
@@ -557,14 +666,16 @@ def main():
     if not ((eo_h[:, 2] == 0).all() and (eo_h[:, 1] == E).all() and (eo_h[:, 0] == 0).all()):
         raise RuntimeError(f"a pipelined step failed: statuses {set(eo_h[:, 2].tolist())}, counts {set(eo_h[:, 1].tolist())}")
 
-    # Latency: synchronous calls, each waiting for its edge count on the host.
+    # Latency: synchronous calls, each waiting for its edge count on the host
+    # (at least LATENCY_SAMPLES of them, so that p99 is not the maximum).
     lat = []
+    n_lat = max(LATENCY_SAMPLES, args.steps)
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(n_lat):
         a = time.perf_counter()
         step()
         lat.append(time.perf_counter() - a)
-    sync_events_per_s = args.steps / (time.perf_counter() - t1)
+    sync_events_per_s = n_lat / (time.perf_counter() - t1)
 
     # Same steps again with HIP events around every stage (on the stream the
     # kernels run on) for the per-kernel durations of the roofline.
@@ -581,15 +692,26 @@ def main():
     dpad = next(p for p in (4, 8, 12, 16, 24, 32, 48, 64) if d <= p)
     t_search = stage_ms["search"] * 1e-3
     sb = search_bytes(n, dpad, st["n_cells"], E)
+    # Algorithmic work of the search: 3d + 1 FP32 operations (d differences, d
+    # squares, d sums, one comparison) per examined pair, no early exit counted.
     ops = st["candidates"] * (3 * d + 1)
-    roofline = {"bound": "alu", "achieved": ops / t_search / 1e12, "peak": VALU_PEAK_TOPS,
-                "unit": "TFLOP/s", "frac": ops / t_search / 1e12 / VALU_PEAK_TOPS,
-                "traffic": stored_traffic("k_search<8, false>") if dpad == 8 and spec.K >= 16 else None,
-                "valu_issue_util": stored_valu("k_search<8, false>") if dpad == 8 and spec.K >= 16 else None,
-                "kernel": "k_search", "kernel_us": t_search * 1e6,
-                "work": f"{st['candidates']} candidate pairs x (3d+1) FP32 ops",
+    # Executed work: every examined pair gets its leading terms (two for rows of up to
+    # 8 floats, four for 12-float rows, three for wider ones) and a comparison; pairs
+    # below r2 after them get the remaining terms of the padded row and a comparison.
+    lead = 2 if dpad <= 8 else (4 if dpad == 12 else 3)
+    executed = st["candidates"] * (3 * lead + 1) + st["survivors"] * (3 * (dpad - lead) + 1)
+    kname = f"k_search<{dpad}, {'true' if spec.K < 16 else 'false'}>"
+    roofline = {"bound": "alu", "achieved": ops / t_search / 1e12, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ops / t_search / 1e12 / FP32_PEAK_TFLOPS,
+                "traffic": stored_traffic(kname) if args.workload == "single" else None, "kernel": kname, "kernel_us": t_search * 1e6,
+                "work": f"{st['candidates']} examined pairs x (3d+1) FP32 ops = {ops}",
                 "timing": "HIP events on the call's stream around the search kernel, averaged over a second "
-                          "pass of the same steps"}
+                          "pass of the same steps",
+                "plain_lane_peak": PLAIN_LANE_PEAK_TOPS,
+                "frac_of_plain_lane_peak": ops / t_search / 1e12 / PLAIN_LANE_PEAK_TOPS,
+                "executed_ops": executed, "survivors": st["survivors"],
+                "executed_frac": executed / t_search / 1e12 / FP32_PEAK_TFLOPS,
+                "valu_issue_util": stored_valu(kname) if args.workload == "single" else None}
     roofline_hbm = {"bound": "hbm", "achieved": sb / t_search / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": sb / t_search / 1e9 / HBM_PEAK_GBS, "bytes": sb}
     t_step = wall / args.steps
@@ -609,11 +731,15 @@ def main():
                   "count to the host",
         "sync_events_per_s": sync_events_per_s,
         "p50_ms": lat_ms[len(lat_ms) // 2], "p99_ms": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))],
+        "latency_samples": n_lat,
         "path_hbm_gbs": pb / t_step / 1e9, "path_hbm_frac": pb / t_step / 1e9 / HBM_PEAK_GBS,
+        "path_hbm_target_frac": PATH_HBM_TARGET, "path_bytes": pb,
         "stage_us": {k: v * 1e3 for k, v in stage_ms.items()},
         "candidates": st["candidates"],
         "roofline": roofline, "roofline_hbm": roofline_hbm,
     }
+    result["identity"] = identity()
+    result["copy_bandwidth"] = copy_bandwidth()
     if args.workload == "single" and not args.no_labeling:
         result["labeling"] = labeling_bench(spec, X, pts, args.steps, args.warmup, log, not args.no_cpu_baseline)
     if not args.no_batched:

@@ -102,6 +102,8 @@ typedef struct frnn_stats {
     int32_t capped_queries;     /* queries with |N(i)| > K */
     int32_t overflow_queries;   /* queries handled by the long-list path */
     float stage_ms[FRNN_STAGES]; /* per-stage device time with FRNN_FLAG_TIMING, else 0 */
+    int64_t survivors;          /* examined pairs whose leading partial sum stayed below r2, so
+                                   that the search added the remaining terms of the distance */
 } frnn_stats;
 
 /* Bytes of device workspace frnn_build needs for n points of dimension d and
@@ -160,10 +162,14 @@ int frnn_build_batch(const float *points, const int64_t *event_offsets, int32_t 
  *                        also when it exceeds edge_capacity), then a status word:
  *                        0 ok, FRNN_ERR_NONFINITE or FRNN_ERR_CAPACITY.
  * The total row count must be positive.  FRNN_FLAG_TIMING is not accepted.  With
- * FRNN_FLAG_EVENTS_RESIDENT (see above) only kernels are enqueued, so the call can
- * be captured into a HIP graph; the points, workspace and outputs must then stay
- * at the same addresses for every replay.  Calls that share a workspace must not
- * overlap in time. */
+ * more than one event the event table is copied to the workspace first, from
+ * pinned staging memory the library keeps per calling thread (a call may wait for
+ * that thread's copy of four calls earlier to have run); that copy cannot be
+ * captured, so a call that needs it on a capturing stream returns FRNN_ERR_ARG.
+ * With FRNN_FLAG_EVENTS_RESIDENT (see above) only kernels are enqueued, so the
+ * call can be captured into a HIP graph; the points, workspace and outputs must
+ * then stay at the same addresses for every replay.  Calls that share a workspace
+ * must not overlap in time. */
 int frnn_build_batch_async(const float *points, const int64_t *event_offsets, int32_t n_events, int32_t d,
                            float r, int32_t K, void *workspace, size_t workspace_bytes,
                            int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *edge_offsets_device,

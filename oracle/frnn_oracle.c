@@ -107,7 +107,8 @@ static int64_t emit_query(int64_t i, hits_t *h, int K, int64_t *src, int64_t *ds
         qsort(h->v, (size_t)h->len, sizeof(hit_t), cmp_hit_dist_then_index);
         keep = K;
     }
-    qsort(h->v, (size_t)keep, sizeof(hit_t), cmp_hit_index);
+    if (keep > 1) /* an empty list has no storage yet, and qsort needs a valid base */
+        qsort(h->v, (size_t)keep, sizeof(hit_t), cmp_hit_index);
     for (int64_t t = 0; t < keep; ++t) {
         if (at + t < cap) {
             src[at + t] = i;

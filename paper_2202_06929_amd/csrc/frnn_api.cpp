@@ -82,6 +82,50 @@ int search_blocks_cached(int dpad, bool sel) {
     return b;
 }
 
+// Event tables of batched calls are copied to the device from pinned host memory
+// that stays valid until the copy has run: a small ring of staging buffers per
+// calling thread, each reused only after the event recorded behind its last copy
+// has completed.
+struct Staging {
+    EventDesc *host = nullptr;
+    size_t count = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+constexpr int kStagingSlots = 4;
+thread_local Staging t_staging[kStagingSlots];
+thread_local int t_staging_next = 0;
+
+// Copies n_events descriptors to dev on the stream through the next staging slot.
+int upload_events(const EventDesc *descs, int n_events, EventDesc *dev, hipStream_t stream) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return FRNN_ERR_HIP;
+    if (cap != hipStreamCaptureStatusNone) return FRNN_ERR_ARG;  // captured calls pass FRNN_FLAG_EVENTS_RESIDENT
+    Staging &st = t_staging[t_staging_next];
+    t_staging_next = (t_staging_next + 1) % kStagingSlots;
+    if (st.pending) {
+        if (hipEventSynchronize(st.done) != hipSuccess) return FRNN_ERR_HIP;
+        st.pending = false;
+    }
+    if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) return FRNN_ERR_HIP;
+    if (st.count < static_cast<size_t>(n_events)) {
+        if (st.host && hipHostFree(st.host) != hipSuccess) return FRNN_ERR_HIP;
+        st.host = nullptr;
+        st.count = 0;
+        void *p = nullptr;
+        const size_t want = static_cast<size_t>(n_events) < 64 ? 64 : static_cast<size_t>(n_events);
+        if (hipHostMalloc(&p, sizeof(EventDesc) * want, hipHostMallocDefault) != hipSuccess) return FRNN_ERR_HIP;
+        st.host = static_cast<EventDesc *>(p);
+        st.count = want;
+    }
+    memcpy(st.host, descs, sizeof(EventDesc) * n_events);
+    if (hipMemcpyAsync(dev, st.host, sizeof(EventDesc) * n_events, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipEventRecord(st.done, stream) != hipSuccess)
+        return FRNN_ERR_HIP;
+    st.pending = true;
+    return FRNN_OK;
+}
+
 thread_local Report *t_report = nullptr;    // pinned host copy of the device report
 thread_local Report *t_report_dev = nullptr;  // its device-visible address (null: copy instead)
 thread_local hipEvent_t t_events[FRNN_STAGES + 1] = {};
@@ -135,7 +179,7 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.tpos = cv.take<unsigned long long>(rows);
     ws.heavy = cv.take<HeavyEntry>(rows);
     ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap + static_cast<size_t>(edge_capacity));
-    ws.tested = cv.take<unsigned long long>(kMaxSearchBlocks);
+    ws.tested = cv.take<unsigned long long>(2 * kMaxSearchBlocks);
     ws.capped_blk = cv.take<unsigned int>(kMaxSearchBlocks);
     ws.rows = rows;
     ws.cells = cells;
@@ -234,11 +278,11 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
         }
         a.events = t_events;
     }
-    // Batches: descriptors go to the device first (a pageable copy; the source is
-    // consumed before the call returns).
-    if (n_events > 1 && upload &&
-        hipMemcpyAsync(ws.ev, descs, sizeof(EventDesc) * n_events, hipMemcpyHostToDevice, stream) != hipSuccess)
-        return FRNN_ERR_HIP;
+    // Batches: descriptors go to the device first, from pinned staging memory.
+    if (n_events > 1 && upload) {
+        const int us = upload_events(descs, n_events, ws.ev, stream);
+        if (us != FRNN_OK) return us;
+    }
     if (enqueue_build(a, ws) != hipSuccess) return FRNN_ERR_HIP;
     *ws_out = ws;
     *timing_out = timing;
@@ -282,6 +326,7 @@ int run(const EventDesc *descs, int n_events, long long rows, long long cells, i
     if (stats) {
         stats->n_edges = rep_out->n_edges;
         stats->candidates = static_cast<int64_t>(rep_out->tested);
+        stats->survivors = static_cast<int64_t>(rep_out->survived);
         stats->n_cells = rep_out->n_cells;
         for (int p = 0; p < 3; ++p) {
             stats->grid[p] = rep_out->G[p];

@@ -74,6 +74,7 @@ struct Counters {
 struct Report {
     long long n_edges;
     unsigned long long tested;
+    unsigned long long survived;  // pairs that passed the first-stage partial test
     int abort;
     unsigned int capped;
     unsigned int heavy;
@@ -111,7 +112,7 @@ struct Workspace {
     unsigned long long *tpos;   // [rows] where each query's list sits in `temp`
     HeavyEntry *heavy;          // [rows]
     unsigned int *temp;         // [rows * kListCap + edge_capacity] neighbour lists
-    unsigned long long *tested; // [kMaxSearchBlocks] pairs examined per search workgroup
+    unsigned long long *tested; // [2 kMaxSearchBlocks] pairs examined, then pairs fully tested, per search workgroup
     unsigned int *capped_blk;   // [kMaxSearchBlocks] capped queries per search workgroup
     long long rows;
     long long cells;

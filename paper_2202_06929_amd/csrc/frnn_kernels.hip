@@ -567,6 +567,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     __shared__ unsigned long long ring_all[kWaves][kRing];
     __shared__ float racc_all[DP <= 8 ? kWaves : 1][DP <= 8 ? kRing : 1];
     __shared__ unsigned long long tested_w[kWaves];
+    __shared__ unsigned long long survived_w[kWaves];
     __shared__ unsigned int capped_w[kWaves];
     if (ctr->abort) return;
     unsigned int *lst = lst_all[wave_id()];
@@ -591,6 +592,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     // 8 floats; wider rows exchange the candidate's coordinates between lanes instead.
     constexpr bool kRowRing = DP <= 8;
     unsigned long long tested = 0;
+    unsigned long long survived = 0;  // pairs that reached the second stage
 
     // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
     // workgroups of one XCD take consecutive queries and share their rows in its L2.
@@ -790,6 +792,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 }
                 const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
                 tested += static_cast<unsigned long long>(Qn) * M;
+                survived += tail;
                 wave_lds_sync();
                 // Kept counts for every query; lists that fit are stored at a fixed place
                 // (kListCap slots per sorted row), longer ones go to the long-list kernel.
@@ -887,17 +890,20 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     capped = wave_sum(capped);
     if (lane == 0) {
         tested_w[wave_id()] = tested;
+        survived_w[wave_id()] = survived;
         capped_w[wave_id()] = capped;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0;
+        unsigned long long t = 0, sv = 0;
         unsigned int c = 0;
         for (int w = 0; w < kWaves; ++w) {
             t += tested_w[w];
+            sv += survived_w[w];
             c += capped_w[w];
         }
         tested_out[blockIdx.x] = t;
+        tested_out[kMaxSearchBlocks + blockIdx.x] = sv;
         capped_out[blockIdx.x] = c;
     }
 }
@@ -1124,19 +1130,22 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     const long long E = static_cast<long long>(tot);
     const bool overflow = static_cast<unsigned long long>(E) > cap || ctr->heavy_top > heavy_cap;
     if (b == 0) {
-        unsigned long long t = 0, cp = 0;
+        unsigned long long t = 0, sv = 0, cp = 0;
         if (!abort)
             for (int k = threadIdx.x; k < search_blocks; k += kPlaceBlock) {
                 t += tested[k];
+                sv += tested[kMaxSearchBlocks + k];
                 cp += capped_blk[k];
             }
         t = block_sum(t, scratch);
+        sv = block_sum(sv, scratch);
         cp = block_sum(cp, scratch);
         if (threadIdx.x == 0) {
             const Plan P = plans[0];
             Report rep;
             rep.n_edges = E;
             rep.tested = t;
+            rep.survived = sv;
             rep.abort = abort ? 1 : 0;
             rep.capped = static_cast<unsigned int>(cp);
             rep.heavy = ctr->heavy_count;

@@ -45,13 +45,13 @@ class FrnnStats(ctypes.Structure):
                 ("n_cells", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
                 ("dims", ctypes.c_int32 * 3), ("cell", ctypes.c_float * 3),
                 ("capped_queries", ctypes.c_int32), ("overflow_queries", ctypes.c_int32),
-                ("stage_ms", ctypes.c_float * 7)]
+                ("stage_ms", ctypes.c_float * 7), ("survivors", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {"n_edges": self.n_edges, "candidates": self.candidates, "n_cells": self.n_cells,
                 "grid": list(self.grid), "dims": list(self.dims), "cell": list(self.cell),
                 "capped_queries": self.capped_queries, "overflow_queries": self.overflow_queries,
-                "stage_ms": dict(zip(STAGES, self.stage_ms))}
+                "stage_ms": dict(zip(STAGES, self.stage_ms)), "survivors": self.survivors}
 
 
 @dataclasses.dataclass(frozen=True)

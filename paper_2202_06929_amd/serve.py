@@ -21,7 +21,7 @@ from typing import Callable, Protocol
 
 import numpy as np
 
-OK, REJECTED, FAILED = 0, -1, -2
+OK, REJECTED, FAILED, CANCELLED, TIMED_OUT = 0, -1, -2, -3, -4
 
 
 @dataclasses.dataclass
@@ -35,6 +35,7 @@ class Request:
     status: int | None = None   # OK, REJECTED, FAILED or a library status
     edges: object = None        # int64 [2, E] (device tensor for the GPU executor)
     batch: int | None = None
+    timeout: float | None = None  # seconds after arrival by which the request must have started
 
     @property
     def n(self) -> int:
@@ -51,6 +52,7 @@ class Executor(Protocol):
     def start(self, batch: list[Request]) -> object: ...
     def poll(self, handle: object) -> bool: ...
     def finish(self, handle: object) -> list[tuple[int, object]]: ...
+    def abort(self, handle: object) -> None: ...
     def release(self, req: Request) -> None: ...
     def free_streams(self) -> int: ...
 
@@ -60,6 +62,8 @@ class ServerStats:
     completed: int
     rejected: int
     failed: int
+    cancelled: int
+    timed_out: int
     batches: int
     wall: float
     p50_ms: float
@@ -74,7 +78,13 @@ class ServerStats:
 
 
 class Server:
-    """Admission by slots and HBM budget, batching, completion tracking."""
+    """Admission by slots and HBM budget, batching, completion tracking.
+
+    A request that has not started may be cancelled (cancel(rid)) or may carry a
+    timeout (seconds after its arrival by which it must have started); either way
+    it completes without running, with status CANCELLED or TIMED_OUT, and its
+    admission (slot and budget) is returned.  Work already on the GPU runs to its
+    end."""
 
     def __init__(self, executor: Executor, hbm_budget: int, max_slots: int = 256, max_batch: int = 64,
                  clock: Callable[[], float] | None = None, idle: Callable[[float], None] | None = None):
@@ -87,9 +97,23 @@ class Server:
         self.used = 0
         self.in_flight: list[tuple[object, list[Request]]] = []
         self.slots = 0
+        self._cancel: set[int] = set()
+        self._timeouts = False
+
+    def cancel(self, rid: int) -> None:
+        """Cancels request rid if it has not started by the server's next look at it."""
+        self._cancel.add(rid)
+
+    def _dropped(self, req: Request, now: float) -> int | None:
+        if req.rid in self._cancel:
+            return CANCELLED
+        if req.timeout is not None and now > req.arrival + req.timeout:
+            return TIMED_OUT
+        return None
 
     def run(self, trace: list[Request]) -> ServerStats:
         pending = deque(sorted(trace, key=lambda q: q.arrival))
+        self._timeouts = any(q.timeout is not None for q in trace)
         waiting: deque[Request] = deque()    # arrived, not admitted
         admitted: deque[Request] = deque()   # admitted, not started
         done: list[Request] = []
@@ -101,6 +125,23 @@ class Server:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
+            # Cancelled or expired requests leave before they take (or after they
+            # return) a slot and their share of the budget.
+            for queue, holds in ((waiting, False), (admitted, True)):
+                if not queue or not (self._cancel or self._timeouts):
+                    continue
+                keep = deque()
+                for req in queue:
+                    why = self._dropped(req, now)
+                    if why is None:
+                        keep.append(req)
+                    elif holds:
+                        self._complete(req, why, None, now, done)
+                    else:
+                        req.status, req.done = why, now
+                        done.append(req)
+                queue.clear()
+                queue.extend(keep)
             # Admission in arrival order: a free slot and room in the budget.
             while waiting and self.slots < self.max_slots:
                 req = waiting[0]
@@ -133,7 +174,8 @@ class Server:
                 batches += 1
                 batch_sizes.append(len(batch))
             max_in_flight = max(max_in_flight, sum(len(b) for _, b in self.in_flight))
-            # Completions.
+            # Completions.  A batch whose poll or finish raises fails as a whole and
+            # gives its stream back through abort().
             still = []
             for handle, batch in self.in_flight:
                 try:
@@ -144,10 +186,14 @@ class Server:
                     still.append((handle, batch))
                     continue
                 t_done = self.clock() - t0
-                try:
-                    results = self.ex.finish(handle) if ready else None
-                except Exception:
-                    results = None
+                results = None
+                if ready:
+                    try:
+                        results = self.ex.finish(handle)
+                    except Exception:
+                        results = None
+                if results is None:
+                    self.ex.abort(handle)
                 for k, req in enumerate(batch):
                     st, edges = results[k] if results is not None else (FAILED, None)
                     self._complete(req, st, edges, t_done, done)
@@ -159,7 +205,9 @@ class Server:
         n_ok = int(lat.size)
         return ServerStats(
             completed=n_ok, rejected=sum(r.status == REJECTED for r in done),
-            failed=sum(r.status not in (OK, REJECTED) for r in done), batches=batches, wall=wall,
+            failed=sum(r.status not in (OK, REJECTED, CANCELLED, TIMED_OUT) for r in done),
+            cancelled=sum(r.status == CANCELLED for r in done), timed_out=sum(r.status == TIMED_OUT for r in done),
+            batches=batches, wall=wall,
             p50_ms=float(np.percentile(lat, 50)) if n_ok else float("nan"),
             p99_ms=float(np.percentile(lat, 99)) if n_ok else float("nan"),
             mean_ms=float(lat.mean()) if n_ok else float("nan"),
@@ -193,7 +241,7 @@ def plain_loop(trace: list[Request], build: Callable[[Request], object],
         lat.append(req.latency * 1e3)
     wall = clock() - t0
     lat = np.array(lat)
-    return ServerStats(completed=len(lat), rejected=0, failed=0, batches=len(lat), wall=wall,
+    return ServerStats(completed=len(lat), rejected=0, failed=0, cancelled=0, timed_out=0, batches=len(lat), wall=wall,
                        p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                        mean_ms=float(lat.mean()), events_per_s=len(lat) / wall, max_in_flight=1, mean_batch=1.0)
 
@@ -203,8 +251,15 @@ class GpuExecutor:
 
     Requests hold their points on the device already (the embedding stage that
     produces them runs on the GPU).  A batch passes the events' device pointers to
-    the library, which searches each event on its own grid; outputs and workspaces
-    come from PyTorch's caching allocator and stay on the device until released.
+    the library, which searches each event on its own grid.  Its workspace and edge
+    buffer come from PyTorch's caching allocator on the batch's stream (a memory
+    pool: no device allocation call once the pool is warm).  When the batch
+    completes, the workspace goes back to the pool at once; each request receives a
+    view of the edge buffer, recorded on the completing thread's current stream so
+    that the pool does not hand the memory out again while that stream may still
+    read it; the buffer returns to the pool when the last view is dropped.
+    `live_bytes` counts the workspace and edge-buffer bytes of batches not yet
+    completed.
     """
 
     def __init__(self, r: float, K: int, d: int, n_streams: int = 3, config=None, edges_per_point: int = 16,
@@ -219,6 +274,7 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.busy = [False] * n_streams
+        self.live_bytes = 0
 
     def footprint(self, req: Request) -> int:
         n = max(req.n, 1)
@@ -254,22 +310,37 @@ class GpuExecutor:
             done = torch.cuda.Event()
             done.record(s)
         self.busy[k] = True
-        return {"stream": k, "event": done, "out": out, "eo": eo, "batch": batch, "ws": ws}
+        held = ws.numel() + out.numel() * 8
+        self.live_bytes += held
+        return {"stream": k, "event": done, "out": out, "eo": eo, "batch": batch, "ws": ws, "held": held}
 
     def poll(self, handle) -> bool:
         return handle["event"].query()
 
+    def _drop(self, handle) -> None:
+        """Gives the batch's stream back and its workspace to the pool (once)."""
+        if handle.get("held"):
+            self.busy[handle["stream"]] = False
+            self.live_bytes -= handle["held"]
+            handle["held"] = 0
+            handle["ws"] = None
+
+    def abort(self, handle) -> None:
+        self._drop(handle)
+        handle["out"] = None
+
     def finish(self, handle):
-        frnn = self.frnn
-        self.busy[handle["stream"]] = False
+        torch, frnn = self.torch, self.frnn
+        self._drop(handle)
         eo = handle["eo"].cpu().numpy()
         batch = handle["batch"]
+        out = handle.pop("out")
         status = int(eo[-1])
         if status == 3:  # more edges than the guess: rebuild each event with exact room
             return [(OK, frnn.build(req.points, self.r, self.K, self.config)) for req in batch]
         if status != 0:
             return [(status, None) for _ in batch]
-        out = handle["out"]
+        out.record_stream(torch.cuda.current_stream(self.device))
         return [(OK, out[:, int(eo[k]):int(eo[k + 1])]) for k in range(len(batch))]
 
     def release(self, req: Request) -> None:

@@ -50,6 +50,10 @@ def cache_key(arch: str, d: int, rows: int, r: float, K: int) -> str:
     return f"{arch}|d={d}|b={size_bucket(rows)}|r={r:.6g}|K={K}"
 
 
+def _sync() -> None:
+    torch.cuda.synchronize()
+
+
 def _arch() -> str:
     props = torch.cuda.get_device_properties(0)
     return getattr(props, "gcnArchName", props.name).split(":")[0]
@@ -93,7 +97,7 @@ def tune(points: torch.Tensor, offsets, r: float, K: int, repeats: int = 5,
                 raise AssertionError(f"config {cfg} changed the edges: the search is not exact")
             ts = []
             for _ in range(repeats):
-                torch.cuda.synchronize()
+                _sync()
                 t0 = time.perf_counter()
                 frnn.build_batch_into(points, off, r, K, ws, out[0], out[1], cfg)
                 ts.append(time.perf_counter() - t0)

@@ -29,12 +29,14 @@ class SimClock:
 class FakeExecutor:
     """Runs the oracle per event; a batch takes 50 us + 10 ns per point."""
 
-    def __init__(self, clock, n_streams=2, fail_batches=(), fail_finish=(), bytes_per_point=100):
+    def __init__(self, clock, n_streams=2, fail_batches=(), fail_finish=(), fail_poll=(), bytes_per_point=100):
         self.clock = clock
         self.n_streams = n_streams
         self.busy = 0
         self.fail_batches = set(fail_batches)
         self.fail_finish = set(fail_finish)
+        self.fail_poll = set(fail_poll)
+        self.aborted = []
         self.bpp = bytes_per_point
         self.batches = 0
         self.admitted = []
@@ -61,13 +63,24 @@ class FakeExecutor:
         return {"b": b, "ready": self.clock.now + cost, "batch": batch}
 
     def poll(self, h):
+        if h["b"] in self.fail_poll and self.clock.now >= h["ready"]:
+            raise RuntimeError("injected poll failure")
         return self.clock.now >= h["ready"]
 
+    def _free(self, h):
+        if not h.get("freed"):
+            h["freed"] = True
+            self.busy -= 1
+
     def finish(self, h):
-        self.busy -= 1
+        self._free(h)
         if h["b"] in self.fail_finish:
             raise RuntimeError("injected finish failure")
         return [(serve.OK, oracle.frnn_grid(r.points, R, K)) for r in h["batch"]]
+
+    def abort(self, h):
+        self.aborted.append(h["b"])
+        self._free(h)
 
     def release(self, req):
         self.live.discard(req.rid)
@@ -87,7 +100,8 @@ def make_trace(n_events=40, rate=20000.0, seed=3, lo=20, hi=400):
 
 def run(trace, budget=10**9, **kw):
     clock = SimClock()
-    ex = FakeExecutor(clock, **{k: v for k, v in kw.items() if k in ("n_streams", "fail_batches", "fail_finish")})
+    ex = FakeExecutor(clock, **{k: v for k, v in kw.items()
+                                if k in ("n_streams", "fail_batches", "fail_finish", "fail_poll")})
     srv = serve.Server(ex, hbm_budget=budget, max_slots=kw.get("max_slots", 64), max_batch=kw.get("max_batch", 8),
                        clock=clock, idle=clock.idle)
     stats = srv.run(trace)
@@ -142,10 +156,10 @@ def test_slot_limit_bounds_requests_in_flight():
     assert stats.completed == len(trace)
 
 
-@pytest.mark.parametrize("where", ["start", "finish"])
+@pytest.mark.parametrize("where", ["start", "finish", "poll"])
 def test_injected_executor_failure_fails_only_that_batch(where):
     trace = make_trace(n_events=30)
-    kw = {"fail_batches": {2}} if where == "start" else {"fail_finish": {1}}
+    kw = {"start": {"fail_batches": {2}}, "finish": {"fail_finish": {1}}, "poll": {"fail_poll": {1}}}[where]
     srv, ex, stats = run(trace, **kw)
     failed = [r for r in trace if r.status == serve.FAILED]
     assert failed and len({r.batch for r in failed}) == 1
@@ -168,3 +182,62 @@ def test_plain_loop_baseline():
     assert stats.completed == 10 and stats.p50_ms > 0.05
     for req in trace:
         assert req.latency >= 50e-6
+
+
+def test_poll_failures_give_every_stream_back():
+    """A batch whose completion check raises is aborted, so its stream is free
+    again: with every batch failing that way the server still drains the trace
+    (it would spin forever if the streams stayed taken)."""
+    trace = make_trace(n_events=20, rate=1e6)
+    srv, ex, stats = run(trace, n_streams=2, fail_poll=set(range(100)))
+    assert stats.failed == len(trace) and stats.completed == 0
+    assert ex.busy == 0 and sorted(ex.aborted) == list(range(stats.batches))
+    assert srv.used == 0 and srv.slots == 0 and not ex.live
+
+
+def test_cancelled_requests_never_run_and_return_their_admission():
+    """Requests cancelled while queued (waiting for admission, or admitted but not
+    yet started) complete as CANCELLED without reaching the executor; the others
+    finish with the oracle's edges; slots and budget return to zero."""
+    trace = make_trace(n_events=30, rate=1e6)  # all arrive at once; one stream, batches of 2
+    clock = SimClock()
+    ex = FakeExecutor(clock, n_streams=1)
+    srv = serve.Server(ex, hbm_budget=10 ** 9, max_slots=64, max_batch=2, clock=clock, idle=clock.idle)
+    started = []
+    orig_start = ex.start
+
+    def start(batch):
+        started.extend(r.rid for r in batch)
+        if len(started) == 2:   # while the first batch runs, cancel three queued requests
+            for rid in (5, 11, 29):
+                srv.cancel(rid)
+        return orig_start(batch)
+
+    ex.start = start
+    srv.cancel(17)  # cancelled before it arrives
+    stats = srv.run(trace)
+    cancelled = sorted(r.rid for r in trace if r.status == serve.CANCELLED)
+    assert cancelled == [5, 11, 17, 29] and stats.cancelled == 4
+    assert not set(cancelled) & set(started)
+    assert stats.completed == len(trace) - 4
+    for r in trace:
+        if r.status == serve.OK:
+            assert np.array_equal(r.edges, oracle.frnn_grid(r.points, R, K))
+    assert srv.used == 0 and srv.slots == 0 and not ex.live
+
+
+def test_requests_that_wait_past_their_timeout_time_out():
+    """With one stream and a burst of arrivals, requests whose timeout passes
+    before they can start complete as TIMED_OUT; a generous timeout never fires."""
+    trace = make_trace(n_events=24, rate=1e6)
+    for k, r in enumerate(trace):
+        r.timeout = 1.0 if k % 2 else 150e-6
+    srv, ex, stats = run(trace, n_streams=1, max_batch=2)
+    late = [r for r in trace if r.status == serve.TIMED_OUT]
+    assert late and stats.timed_out == len(late)
+    assert all(r.timeout == 150e-6 for r in late)
+    for r in trace:
+        if r.status == serve.OK:
+            assert r.started - r.arrival <= r.timeout + 1e-5
+    assert stats.completed + stats.timed_out == len(trace)
+    assert srv.used == 0 and srv.slots == 0 and not ex.live
