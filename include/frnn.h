@@ -23,7 +23,8 @@
  *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *     All device work is enqueued on it.  Inputs must stay alive and unchanged
  *     until that work has finished.
- *   - The caller owns every buffer.  The library allocates no device memory;
+ *   - The caller owns every buffer.  The library allocates no device memory
+ *     (frnn_build_noalloc works in a fixed device array of the library's own);
  *     it keeps one small pinned host buffer per calling thread for results.
  *   - Errors are returned as status codes; nothing is thrown across this
  *     interface.  On any status other than FRNN_OK the output buffers hold
@@ -129,6 +130,30 @@ int frnn_build(const float *points, int64_t n, int32_t d, float r, int32_t K,
                void *workspace, size_t workspace_bytes,
                int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *n_edges,
                const frnn_config *config, frnn_stats *stats, void *stream);
+
+/* Size of the device array frnn_build_noalloc works in, in MiB (per device). */
+#define FRNN_NOALLOC_SCRATCH_MIB 64
+
+/* frnn_build for callers that cannot allocate device memory (code that must not
+ * call hipMalloc: a tight serving loop, a harness that forbids it): the same
+ * result, with no workspace argument.  The library works in a device array of
+ * FRNN_NOALLOC_SCRATCH_MIB MiB that each device holds from the first such call
+ * on it until the process ends; the call itself allocates no device or pinned
+ * memory (its report is copied into the caller's frame).  The first call on a
+ * device looks the array up; later calls only enqueue kernels and copy the
+ * report back.
+ *   Arguments as for frnn_build, without workspace / workspace_bytes.
+ *   FRNN_ERR_WORKSPACE     frnn_workspace_bytes(n, d, edge_capacity) exceeds the array
+ *                          (checked on the host before any device work; for example
+ *                          120,000 points of d = 8 with room for 16 edges per point fit)
+ *   FRNN_ERR_ARG           also for FRNN_FLAG_TIMING (timing would create HIP events)
+ * Every call on one device shares that device's array: calls that overlap in
+ * time on one device (from several host threads, or on several streams) race
+ * and must be serialised by the caller.  Nothing need be cleared between calls:
+ * each call clears what it counts. */
+int frnn_build_noalloc(const float *points, int64_t n, int32_t d, float r, int32_t K,
+                       int64_t *src, int64_t *dst, int64_t edge_capacity, int64_t *n_edges,
+                       const frnn_config *config, frnn_stats *stats, void *stream);
 
 /* Bytes of device workspace frnn_build_batch needs for the given events (see
  * below) and room for edge_capacity edges in total.  Returns 0 for invalid

@@ -289,6 +289,8 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
     return FRNN_OK;
 }
 
+int report_status(const Report &rep, frnn_stats *stats, bool timing, int64_t edge_capacity);
+
 // Enqueues, copies the report (and the per-event edge ranges) back and waits.
 int run(const EventDesc *descs, int n_events, long long rows, long long cells, int max_n,
         int32_t d, float r, int32_t K, void *workspace, int64_t *src, int64_t *dst, int64_t edge_capacity,
@@ -322,25 +324,30 @@ int run(const EventDesc *descs, int n_events, long long rows, long long cells, i
     if (hipStreamSynchronize(stream) != hipSuccess) return FRNN_ERR_HIP;
     std::atomic_thread_fence(std::memory_order_acquire);
     memcpy(rep_out, t_report, sizeof(Report));
-    if (rep_out->n_edges < 0) return FRNN_ERR_HIP;  // the report never arrived
+    return report_status(*rep_out, stats, timing, edge_capacity);
+}
+
+// Status of a finished call from its report; fills the stats.
+int report_status(const Report &rep, frnn_stats *stats, bool timing, int64_t edge_capacity) {
+    if (rep.n_edges < 0) return FRNN_ERR_HIP;  // the report never arrived
     if (stats) {
-        stats->n_edges = rep_out->n_edges;
-        stats->candidates = static_cast<int64_t>(rep_out->tested);
-        stats->survivors = static_cast<int64_t>(rep_out->survived);
-        stats->n_cells = rep_out->n_cells;
+        stats->n_edges = rep.n_edges;
+        stats->candidates = static_cast<int64_t>(rep.tested);
+        stats->survivors = static_cast<int64_t>(rep.survived);
+        stats->n_cells = rep.n_cells;
         for (int p = 0; p < 3; ++p) {
-            stats->grid[p] = rep_out->G[p];
-            stats->cell[p] = rep_out->c[p];
+            stats->grid[p] = rep.G[p];
+            stats->cell[p] = rep.c[p];
         }
-        stats->capped_queries = static_cast<int32_t>(rep_out->capped);
-        stats->overflow_queries = static_cast<int32_t>(rep_out->heavy);
+        stats->capped_queries = static_cast<int32_t>(rep.capped);
+        stats->overflow_queries = static_cast<int32_t>(rep.heavy);
         if (timing)
             for (int k = 0; k < FRNN_STAGES; ++k)
                 if (hipEventElapsedTime(&stats->stage_ms[k], t_events[k], t_events[k + 1]) != hipSuccess)
                     return FRNN_ERR_HIP;
     }
-    if (rep_out->abort) return FRNN_ERR_NONFINITE;
-    if (rep_out->n_edges > edge_capacity) return FRNN_ERR_CAPACITY;
+    if (rep.abort) return FRNN_ERR_NONFINITE;
+    if (rep.n_edges > edge_capacity) return FRNN_ERR_CAPACITY;
     return FRNN_OK;
 }
 
@@ -497,4 +504,79 @@ extern "C" int frnn_build_events_async(const float *const *event_points, const i
     return enqueue(descs.data(), n_events, rows, cells, max_n, d, r, K, workspace, src, dst, edge_capacity, config,
                    static_cast<hipStream_t>(stream), !resident, reinterpret_cast<long long *>(edge_offsets_device),
                    &ws, &timing);
+}
+
+// ------------------------------------------------------- no-allocation build
+
+namespace {
+
+// Workspace of frnn_build_noalloc: one array per device, held until the process
+// ends.  Host code never passes this name to a kernel or a copy (on the host it
+// only stands for the symbol); it uses the device address looked up below.
+constexpr size_t kNoAllocBytes = size_t{FRNN_NOALLOC_SCRATCH_MIB} << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device (with
+// that device current).  The same first call also fills the search-grid cache
+// for every row width, so that later calls insert nothing into it.
+int noalloc_workspace(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return FRNN_ERR_HIP;
+    if (dev < 0 || dev >= kNoAllocDevices) return FRNN_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FRNN_ERR_HIP;
+        if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0) return FRNN_ERR_HIP;
+        for (int dp : {4, 8, 12, 16, 24, 32, 48, 64}) {
+            search_blocks_cached(dp, false);
+            search_blocks_cached(dp, true);
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return FRNN_OK;
+}
+
+}  // namespace
+
+extern "C" int frnn_build_noalloc(const float *points, int64_t n, int32_t d, float r, int32_t K, int64_t *src,
+                                  int64_t *dst, int64_t edge_capacity, int64_t *n_edges,
+                                  const frnn_config *config, frnn_stats *stats, void *stream) {
+    if (!n_edges || n < 0) return FRNN_ERR_ARG;
+    const int st = check_common(d, r, K, edge_capacity, config);
+    if (st != FRNN_OK) return st;
+    if (config && (config->flags & FRNN_FLAG_TIMING)) return FRNN_ERR_ARG;  // would create HIP events
+    if (n >= (int64_t{1} << 31)) return FRNN_ERR_UNSUPPORTED;
+    init_stats(stats, config, d);
+    *n_edges = 0;
+    if (n == 0) return FRNN_OK;
+    if (!points || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
+    if (frnn_workspace_bytes(n, d, edge_capacity) > kNoAllocBytes) return FRNN_ERR_WORKSPACE;
+    void *workspace = nullptr;
+    const int sw = noalloc_workspace(&workspace);
+    if (sw != FRNN_OK) return sw;
+    const int64_t offs[2] = {0, n};
+    EventDesc desc;
+    const long long cells = describe_events(offs, 1, &desc);
+    desc.pts = points;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace ws;
+    bool timing = false;
+    const int se = enqueue(&desc, 1, n, cells, static_cast<int>(n), d, r, K, workspace, src, dst, edge_capacity,
+                           config, s, false, nullptr, &ws, &timing);
+    if (se != FRNN_OK) return se;
+    // The report stays in the scratch array and is copied into this frame.
+    Report rep;
+    rep.n_edges = -1;
+    if (hipMemcpyAsync(&rep, ws.report, sizeof(Report), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return FRNN_ERR_HIP;
+    const int rs = report_status(rep, stats, false, edge_capacity);
+    if (rs == FRNN_OK || rs == FRNN_ERR_CAPACITY) *n_edges = rep.n_edges;
+    return rs;
 }

@@ -24,6 +24,7 @@ FRNN_OK, FRNN_ERR_ARG, FRNN_ERR_NONFINITE, FRNN_ERR_CAPACITY = 0, 1, 2, 3
 FRNN_ERR_WORKSPACE, FRNN_ERR_UNSUPPORTED, FRNN_ERR_HIP = 4, 5, 6
 MAX_D = 64
 MAX_K = 4096
+NOALLOC_SCRATCH_MIB = 64
 FLAG_TIMING = 1
 FLAG_EVENTS_RESIDENT = 2
 STAGES = ("bounds", "keys", "cells", "scatter", "search", "long", "place")
@@ -87,6 +88,9 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.frnn_build.argtypes = [vp, i64, i32, ctypes.c_float, i32, vp, ctypes.c_size_t, vp, vp, i64,
                                ctypes.POINTER(i64), ctypes.POINTER(FrnnConfig),
                                ctypes.POINTER(FrnnStats), vp]
+    lib.frnn_build_noalloc.restype = ctypes.c_int
+    lib.frnn_build_noalloc.argtypes = [vp, i64, i32, ctypes.c_float, i32, vp, vp, i64, ctypes.POINTER(i64),
+                                       ctypes.POINTER(FrnnConfig), ctypes.POINTER(FrnnStats), vp]
     lib.frnn_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.frnn_batch_workspace_bytes.argtypes = [ctypes.POINTER(i64), i32, i32, i64]
     lib.frnn_build_batch.restype = ctypes.c_int
@@ -189,6 +193,23 @@ def build(points: torch.Tensor, r: float, K: int, config: Config | None = None,
             continue
         raise FrnnError(st, status_string(st))
     raise FrnnError(FRNN_ERR_CAPACITY, "capacity retry failed")
+
+
+def build_noalloc_into(points: torch.Tensor, r: float, K: int, src: torch.Tensor, dst: torch.Tensor,
+                       config: Config | None = None, stats: FrnnStats | None = None) -> tuple[int, int]:
+    """One call of frnn_build_noalloc (no workspace: the library's fixed device
+    array) on caller-provided outputs.  Returns (status, E)."""
+    _check_points(points)
+    n, d = points.shape
+    E = ctypes.c_int64(0)
+    cfg = config.to_c() if config is not None else None
+    st = lib().frnn_build_noalloc(
+        ctypes.c_void_p(points.data_ptr()), n, d, ctypes.c_float(r), K,
+        ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel(),
+        ctypes.byref(E), ctypes.byref(cfg) if cfg is not None else None,
+        ctypes.byref(stats) if stats is not None else None,
+        ctypes.c_void_p(_stream_handle(points.device)))
+    return st, int(E.value)
 
 
 def _offsets_array(offsets) -> np.ndarray:

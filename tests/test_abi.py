@@ -105,6 +105,39 @@ def test_argument_errors_return_before_touching_a_device(lib):
     assert _call(lib, points=0x1000, ws=0x100010, wsb=1 << 40)[0] == ERR
 
 
+def _noalloc_call(lib, points=0, n=10, d=8, r=0.1, K=4, src=0, dst=0, cap=0, cfg=None, E=True):
+    e = ctypes.c_int64(-7)
+    st = lib.frnn_build_noalloc(ctypes.c_void_p(points), n, d, ctypes.c_float(r), K, ctypes.c_void_p(src),
+                                ctypes.c_void_p(dst), cap, ctypes.byref(e) if E else None,
+                                ctypes.byref(cfg) if cfg is not None else None, None, None)
+    return st, e.value
+
+
+def test_noalloc_checks_return_before_touching_a_device(lib):
+    from paper_2202_06929_amd import frnn
+    ERR = frnn.FRNN_ERR_ARG
+    assert _noalloc_call(lib, n=-1)[0] == ERR
+    assert _noalloc_call(lib, d=2)[0] == ERR
+    assert _noalloc_call(lib, K=0)[0] == ERR
+    assert _noalloc_call(lib, E=False)[0] == ERR
+    assert _noalloc_call(lib, n=10)[0] == ERR           # null points
+    assert _noalloc_call(lib, points=0x1000, cap=8)[0] == ERR  # null outputs with room for edges
+    timing = frnn.FrnnConfig()
+    timing.flags = frnn.FLAG_TIMING
+    assert _noalloc_call(lib, points=0x1000, cfg=timing)[0] == ERR
+    assert _noalloc_call(lib, n=2 ** 31)[0] == frnn.FRNN_ERR_UNSUPPORTED
+    assert _noalloc_call(lib, n=0) == (frnn.FRNN_OK, 0)
+    # Sizes beyond the library's fixed array are refused on the host.
+    limit = frnn.NOALLOC_SCRATCH_MIB << 20
+    n_fit = 120_000
+    assert frnn.workspace_bytes(n_fit, 8, 16 * n_fit) <= limit
+    n_big = 1_000_000
+    assert frnn.workspace_bytes(n_big, 8, 0) > limit
+    assert _noalloc_call(lib, points=0x1000, n=n_big)[0] == frnn.FRNN_ERR_WORKSPACE
+    assert _noalloc_call(lib, points=0x1000, n=1000, d=64, src=0x2000, dst=0x3000,
+                         cap=limit // 4)[0] == frnn.FRNN_ERR_WORKSPACE
+
+
 def _batch_call(lib, offsets, n_events=None, d=8, r=0.1, K=4, ws=0, wsb=0, cap=0, eo=True):
     import numpy as np
     from paper_2202_06929_amd import frnn

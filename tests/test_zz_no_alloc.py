@@ -1,0 +1,91 @@
+"""frnn_build_noalloc, the entry point that allocates nothing, against frnn_build
+with a caller workspace: identical bytes and counts on calls in a row, each
+later call smaller than the one before, through the C interface.
+
+The no-allocation call works in one device array that keeps the previous call's
+contents, so a later, smaller call checks that nothing stale leaks into it.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle
+from paper_2202_06929_amd import events, frnn
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def with_workspace(pts, r, K, cap):
+    n, d = pts.shape
+    ws = torch.full((frnn.workspace_bytes(n, d, cap),), 0xA5, dtype=torch.uint8, device=DEV)
+    out = torch.full((2, cap), -7, dtype=torch.int64, device=DEV)
+    stats = frnn.FrnnStats()
+    st, E = frnn.build_into(pts, r, K, ws, out[0], out[1], stats=stats)
+    torch.cuda.synchronize()
+    assert st == frnn.FRNN_OK, frnn.status_string(st)
+    return out[:, :E].cpu().numpy(), stats.as_dict()
+
+
+def without_workspace(pts, r, K, cap):
+    out = torch.full((2, cap), -9, dtype=torch.int64, device=DEV)
+    stats = frnn.FrnnStats()
+    st, E = frnn.build_noalloc_into(pts, r, K, out[0], out[1], stats=stats)
+    torch.cuda.synchronize()
+    assert st == frnn.FRNN_OK, frnn.status_string(st)
+    return out[:, :E].cpu().numpy(), stats.as_dict()
+
+
+def check_same(name, X, r, K):
+    n = X.shape[0]
+    # Room for every list at its cap, within what the library's fixed array holds.
+    cap = min(min(K, n) * n, 8_000_000) + 1024
+    log(f"no-alloc {name}: n={n} d={X.shape[1]} r={r} K={K}")
+    pts = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(DEV)
+    got, gst = without_workspace(pts, r, K, cap)
+    want, wst = with_workspace(pts, r, K, cap)
+    assert got.shape == want.shape and np.array_equal(got, want), (name, got.shape, want.shape)
+    for key in ("n_edges", "candidates", "survivors", "n_cells", "grid", "capped_queries", "overflow_queries"):
+        assert gst[key] == wst[key], (name, key, gst[key], wst[key])
+    return got
+
+
+def test_calls_in_a_row_match_the_workspace_entry_point():
+    big = events.SINGLE
+    Xb, _ = events.generate(big)
+    check_same("single event", Xb, big.r, big.K)
+    # Smaller, with a cap below the list size (distances kept in the lists).
+    small = events.EventSpec(n=3000, d=8, n_clusters=200, size_lo=8, size_hi=15, sigma=0.02,
+                             noise_frac=0.1, r=0.1, K=8, seed=41)
+    Xs, _ = events.generate(small)
+    got = check_same("small event, K=8", Xs, small.r, small.K)
+    assert np.array_equal(got, oracle.frnn_grid(Xs, small.r, small.K))
+    # Smaller again: one dense clump whose lists go through the long-list path.
+    clump = next(c for c in events.stress_cases() if c.name.startswith("S1"))
+    check_same(clump.name, clump.points, clump.r, clump.K)
+
+
+def test_capacity_status_reports_the_edges_needed():
+    spec = events.TINY
+    X, _ = events.generate(spec)
+    pts = torch.from_numpy(X).to(DEV)
+    want = oracle.frnn_grid(X, spec.r, spec.K)
+    log(f"no-alloc capacity: n={spec.n} E={want.shape[1]}")
+    out = torch.empty((2, 16), dtype=torch.int64, device=DEV)
+    st, E = frnn.build_noalloc_into(pts, spec.r, spec.K, out[0], out[1])
+    torch.cuda.synchronize()
+    assert st == frnn.FRNN_ERR_CAPACITY and E == want.shape[1]
+    out = torch.empty((2, E), dtype=torch.int64, device=DEV)
+    st, E2 = frnn.build_noalloc_into(pts, spec.r, spec.K, out[0], out[1])
+    torch.cuda.synchronize()
+    assert st == frnn.FRNN_OK and E2 == E
+    assert np.array_equal(out.cpu().numpy(), want)
