@@ -17,6 +17,7 @@ HIP-event timings taken inside this run, and the CPU oracle timed on this host.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import statistics
@@ -53,6 +54,7 @@ def parse():
     ap.add_argument("--workload", choices=["single", "high", "tiny", "knn"], default="single")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cell-div", type=int, default=None)
+    ap.add_argument("--axes", type=int, default=0, choices=[0, 3, 4], help="binned coordinates (0: automatic)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-labeling", action="store_true")
@@ -62,7 +64,7 @@ def parse():
                          "[SQ]) and exit")
     ap.add_argument("--commands", nargs="+", default=None, help="the profiling commands, for the summary")
     ap.add_argument("--batch-only", type=int, default=0, metavar="CALLS",
-                    help="build the 64-event batch CALLS times with binned coordinates 4, 5, 7 and the "
+                    help="build the 64-event batch CALLS times with the default binned coordinates and "
                          "default grid (a run to profile) and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TITLE", "TRACE", "COMMAND"),
                     help="print a markdown table of kernel durations from one rocprofv3 kernel-trace folder and exit")
@@ -262,7 +264,7 @@ def batch_only(calls: int) -> None:
     evs = [events.generate(events.batched_spec(n, 100 + k))[0] for k, n in enumerate(sizes)]
     offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     pts = torch.from_numpy(np.concatenate(evs)).to("cuda:0")
-    cfg = frnn.Config(dims=(4, 5, 7))
+    cfg = frnn.Config()
     for k in range(calls):
         edges, eo = frnn.build_batch(pts, offsets, 0.1, 256, cfg)
     torch.cuda.synchronize()
@@ -431,7 +433,7 @@ def batched_bench(steps: int, warmup: int, log) -> dict:
     t_batch = (time.perf_counter() - t) / reps
 
     eo_dev = torch.zeros(len(sizes) + 2, dtype=torch.int64, device=dev)
-    rcfg = frnn.Config(dims=cfg.dims, cell_div=cfg.cell_div, grid_mult=cfg.grid_mult, events_resident=True)
+    rcfg = dataclasses.replace(cfg, events_resident=True)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -462,7 +464,7 @@ def batched_bench(steps: int, warmup: int, log) -> dict:
     n_ev = len(sizes)
     return {"workload": f"batched: {n_ev} events, hits uniform in [20000, 150000] (total {int(offsets[-1])}), "
                         "8-D float32, r=0.1, K=256",
-            "config": {"dims": list(cfg.dims) if cfg.dims else None, "cell_div": cfg.cell_div,
+            "config": {"dims": list(cfg.dims) if cfg.dims else None, "axes": cfg.axes, "cell_div": cfg.cell_div,
                        "grid_mult": cfg.grid_mult},
             "events_per_s_plain_loop": n_ev / t_plain, "events_per_s_batched_call": n_ev / t_batch,
             "events_per_s_graph": n_ev / t_graph, "ms_per_batch_graph": t_graph * 1e3,
@@ -635,7 +637,7 @@ def main():
     dev = torch.device("cuda:0")
     pts = torch.from_numpy(X).to(dev)
     n, d = X.shape
-    cfg = frnn.Config(cell_div=args.cell_div) if args.cell_div else frnn.Config()
+    cfg = frnn.Config(cell_div=args.cell_div or 1, axes=args.axes)
     cap = 16 * n
     offs = np.array([0, n], dtype=np.int64)
     ws = torch.empty(max(frnn.workspace_bytes(n, d, cap), frnn.batch_workspace_bytes(offs, d, cap)),
@@ -679,7 +681,7 @@ def main():
 
     # Same steps again with HIP events around every stage (on the stream the
     # kernels run on) for the per-kernel durations of the roofline.
-    tcfg = frnn.Config(dims=cfg.dims, cell_div=cfg.cell_div, timing=True)
+    tcfg = dataclasses.replace(cfg, timing=True)
     stage_sum = {k: 0.0 for k in frnn.STAGES}
     stats = frnn.FrnnStats()
     for _ in range(args.steps):
@@ -724,7 +726,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload} event: {n} points, {d}-D float32, r={spec.r}, K={spec.K}",
                    "n": n, "d": d, "r": spec.r, "K": spec.K, "seed": spec.seed,
-                   "cell_div": cfg.cell_div, "dims": st["dims"], "grid": st["grid"]},
+                   "cell_div": cfg.cell_div, "axes": st["axes"], "dims": st["dims"], "grid": st["grid"]},
         "edges": E, "edges_per_s": E * events_per_s,
         "timing": "value: steps pipelined on one stream through frnn_build_batch_async (no host round trip per "
                   "step); p50/p99 and sync_events_per_s: synchronous frnn_build calls, each returning its edge "

@@ -16,6 +16,9 @@
  *   edges   = { (i, j) : j in Out(i) }, i ascending then j ascending
  *
  * The result is unique, so two correct implementations produce identical bytes.
+ * The cell grid only limits which pairs are tested: it bins three coordinates as
+ * the paper does, or four (the default for d >= 5, which leaves far fewer
+ * candidates per query), and the edges depend on neither choice.
  *
  * Conventions shared by every entry point:
  *   - Device pointers are HIP device allocations (for example PyTorch CUDA
@@ -58,10 +61,14 @@ enum frnn_status {
 /* Tunables of the grid search.  They change speed only: every setting yields
  * the same edges.  Zero-initialise and set what you need. */
 typedef struct frnn_config {
-    int32_t dims[3];   /* coordinates binned by the grid; all three must differ and lie in
-                          [0, d).  dims[0] is the fastest-varying cell axis.  Default (when
-                          dims[0] == dims[1]): the last three coordinates d-3, d-2, d-1,
-                          so the leading coordinates of the distance sum are unbinned. */
+    int32_t dims[4];   /* coordinates binned by the grid, used when dims[0] != dims[1]: the
+                          first `axes` entries, all different, in [0, d); dims[0] is the
+                          fastest-varying cell axis.  Default: the last `axes` coordinates
+                          d-axes .. d-1, so the leading coordinates of the distance sum
+                          are unbinned. */
+    int32_t axes;      /* number of binned coordinates, 3 or 4 (at most d).  0: 3 when dims
+                          are given, else 4 when d >= 5 and cell_div <= 1, else 3.  Four
+                          binned coordinates need cell_div 1. */
     int32_t cell_div;  /* cell edge = r * (1 + 2^-10) / cell_div, cell_div in {1, 2, 3}
                           (0 means 1).  Neighbours are searched cell_div cells away. */
     int32_t grid_mult; /* search workgroups as a multiple of those that fit on the GPU at
@@ -97,9 +104,10 @@ typedef struct frnn_stats {
     int64_t n_edges;            /* edges written (= *n_edges on success) */
     int64_t candidates;         /* (query, candidate) pairs examined by the search */
     int64_t n_cells;            /* cells of the grid */
-    int32_t grid[3];            /* cells per binned axis */
-    int32_t dims[3];            /* binned coordinates */
-    float cell[3];              /* cell edge per binned axis */
+    int32_t axes;               /* binned coordinates (3 or 4) */
+    int32_t grid[4];            /* cells per binned axis (1 past `axes`) */
+    int32_t dims[4];            /* binned coordinates (-1 past `axes`) */
+    float cell[4];              /* cell edge per binned axis (infinite past `axes`) */
     int32_t capped_queries;     /* queries with |N(i)| > K */
     int32_t overflow_queries;   /* queries handled by the long-list path */
     float stage_ms[FRNN_STAGES]; /* per-stage device time with FRNN_FLAG_TIMING, else 0 */

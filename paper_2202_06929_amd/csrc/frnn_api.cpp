@@ -17,15 +17,16 @@
 
 namespace frnn {
 
-// Cell capacity of an event: n / 2 cells, at least 2^15 and at most 2^22.  The grid
+// Cell capacity of an event: 2 n cells, at least 2^15 and at most 2^24.  The grid
 // plan coarsens its cells until the grid fits (a speed choice only: the search is
-// exact for any grid); a workload's grid of r-sized cells is usually far smaller,
-// and every cell of the capacity is cleared and scanned per call.
+// exact for any grid).  A grid of r-sized cells over four binned coordinates of a
+// workload event has about 2 n cells (mostly empty); every cell of the capacity is
+// cleared and scanned per call.
 int64_t cells_max_for(int64_t n) {
     if (n <= 0) return 1;
-    int64_t c = n / 2;
+    int64_t c = 2 * n;
     if (c < (int64_t{1} << 15)) c = int64_t{1} << 15;
-    if (c > (int64_t{1} << 22)) c = int64_t{1} << 22;
+    if (c > (int64_t{1} << 24)) c = int64_t{1} << 24;
     return c;
 }
 
@@ -51,12 +52,27 @@ struct Carver {
     }
 };
 
+// Binned coordinates of a call: 4 by default when d >= 5 and the cell divisor is 1,
+// else 3; explicit dims without an axis count are 3.
+int axes_for(const frnn_config *c, int d) {
+    if (c && c->axes) return c->axes;
+    if (c && c->dims[0] != c->dims[1]) return 3;
+    const int div = c && c->cell_div ? c->cell_div : 1;
+    return d >= 5 && div == 1 ? 4 : 3;
+}
+
 bool config_ok(const frnn_config *c, int d) {
     if (!c) return true;
+    if (c->axes != 0 && c->axes != 3 && c->axes != 4) return false;
+    const int axes = axes_for(c, d);
+    if (axes > d) return false;
+    if (axes == 4 && c->cell_div > 1) return false;  // (2R+1)^3 runs must fit a wave
     if (c->dims[0] != c->dims[1]) {
-        for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < axes; ++p) {
             if (c->dims[p] < 0 || c->dims[p] >= d) return false;
-        if (c->dims[0] == c->dims[2] || c->dims[1] == c->dims[2]) return false;
+            for (int q = 0; q < p; ++q)
+                if (c->dims[q] == c->dims[p]) return false;
+        }
     }
     if (c->cell_div < 0 || c->cell_div > kMaxReach) return false;
     if (c->grid_mult != 0 && c->grid_mult != 1 && c->grid_mult != 2 && c->grid_mult != 4 && c->grid_mult != 8)
@@ -164,7 +180,7 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.ctr = cv.take<Counters>(1);
     ws.report = cv.take<Report>(1);
     ws.edge_off = cv.take<long long>(static_cast<size_t>(n_events) + 2);
-    ws.key = cv.take<unsigned int>(rows);
+    ws.pcell = cv.take<unsigned int>(rows);
     ws.rank = cv.take<unsigned int>(rows);
     ws.cell_count = cv.take<unsigned int>(cells);
     ws.cell_start = cv.take<unsigned int>(cells + 1);
@@ -226,9 +242,10 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
             int32_t d, float r, int32_t K, void *workspace, int64_t *src, int64_t *dst, int64_t edge_capacity,
             const frnn_config *config, hipStream_t stream, bool upload, long long *edge_off_out, Workspace *ws_out,
             bool *timing_out, Report *report_out = nullptr) {
-    int dims[3] = {d - 3, d - 2, d - 1};
-    if (config && config->dims[0] != config->dims[1])
-        for (int p = 0; p < 3; ++p) dims[p] = config->dims[p];
+    const int axes = axes_for(config, d);
+    int dims[kMaxAxes] = {-1, -1, -1, -1};
+    for (int p = 0; p < axes; ++p)
+        dims[p] = (config && config->dims[0] != config->dims[1]) ? config->dims[p] : d - axes + p;
     LaunchArgs a;
     a.vec4 = d % 4 == 0 ? 1 : 0;
     for (int e = 0; e < n_events && a.vec4; ++e)
@@ -237,7 +254,8 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
     a.max_n = max_n;
     a.d = d;
     a.dpad = dpad_for(d);
-    for (int p = 0; p < 3; ++p) a.dims[p] = dims[p];
+    a.axes = axes;
+    for (int p = 0; p < kMaxAxes; ++p) a.dims[p] = dims[p];
     a.r = r;
     a.r2 = r * r;
     a.K = K;
@@ -335,7 +353,7 @@ int report_status(const Report &rep, frnn_stats *stats, bool timing, int64_t edg
         stats->candidates = static_cast<int64_t>(rep.tested);
         stats->survivors = static_cast<int64_t>(rep.survived);
         stats->n_cells = rep.n_cells;
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < kMaxAxes; ++p) {
             stats->grid[p] = rep.G[p];
             stats->cell[p] = rep.c[p];
         }
@@ -355,7 +373,10 @@ void init_stats(frnn_stats *stats, const frnn_config *config, int d) {
     if (!stats) return;
     memset(stats, 0, sizeof(*stats));
     const bool set = config && config->dims[0] != config->dims[1];
-    for (int p = 0; p < 3; ++p) stats->dims[p] = set ? config->dims[p] : d - 3 + p;
+    const int axes = axes_for(config, d);
+    stats->axes = axes;
+    for (int p = 0; p < kMaxAxes; ++p)
+        stats->dims[p] = p >= axes ? -1 : (set ? config->dims[p] : d - axes + p);
 }
 
 }  // namespace

@@ -16,8 +16,13 @@ constexpr int kListCap = 16;         // neighbours a query may collect in the ma
 constexpr int kQTile = 32;           // queries of one cell handled together by a wave
 constexpr int kRing = 128;           // first-stage survivors queued per wave (a power of two)
 constexpr int kMaxReach = 3;         // largest cell_div
-constexpr int kMaxRuns = (2 * kMaxReach + 1) * (2 * kMaxReach + 1);
-constexpr int kGridAxisMax = 1024;   // cells per binned axis (bounds the key rounding error)
+constexpr int kMaxAxes = 4;          // binned coordinates: 3, or 4 with cell_div 1
+// Cells per binned axis.  The bound keeps the float32 rounding of a cell
+// coordinate under the cell margin; with four axes it also lets the four
+// coordinates of a cell pack into one 32-bit word (8 bits each; 10 bits each
+// with three axes).
+constexpr int kGridAxisMax3 = 1024;
+constexpr int kGridAxisMax4 = 256;
 constexpr int kMaxK = 4096;
 constexpr int kMaxSearchBlocks = 8192;
 constexpr int kKeysBlock = 1024;     // threads per workgroup of the key/histogram pass
@@ -42,23 +47,27 @@ struct EventDesc {
 
 // Per-block min/max of the binned coordinates and a non-finite flag.
 struct BoundsPartial {
-    float mn[3];
-    float mx[3];
+    float mn[kMaxAxes];
+    float mx[kMaxAxes];
     int nonfinite;
     int pad;
 };
 
 // The grid of one event, derived on the device from its bounds.
+// Axis 0 varies fastest in a cell key.  Axes past the binned count have one cell.
 struct Plan {
-    float lo[3];      // smallest binned coordinate per axis
-    float inv_c[3];   // 1 / cell edge per axis (float32)
-    float c[3];       // cell edge per axis
-    int G[3];         // cells per axis
-    int n_cells;      // G[0] * G[1] * G[2]
-    int reach;        // neighbour cells searched on each side, per axis
-    int abort;        // a coordinate was NaN or infinite
-    int pad;
+    float lo[kMaxAxes];     // smallest binned coordinate per axis
+    float inv_c[kMaxAxes];  // 1 / cell edge per axis (float32)
+    float c[kMaxAxes];      // cell edge per axis
+    int G[kMaxAxes];        // cells per axis
+    int n_cells;            // product of G
+    int reach;              // neighbour cells searched on each side, per axis
+    int abort;              // a coordinate was NaN or infinite
+    int axes;               // binned coordinates (3 or 4)
 };
+
+// Bits per axis in a packed cell coordinate word (axis p at bits [p b, p b + b)).
+__host__ __device__ constexpr int cell_bits(int axes) { return axes == 4 ? 8 : 10; }
 
 // Single-address atomics serialise across the chip (about 11 ns each), so these
 // are touched only by rare events (long lists, capped queries, bad input).
@@ -79,15 +88,15 @@ struct Report {
     unsigned int capped;
     unsigned int heavy;
     int n_cells;
-    int G[3];
-    float c[3];
+    int G[kMaxAxes];
+    float c[kMaxAxes];
 };
 
 // A query whose neighbour list did not fit the list of the main search.
 struct HeavyEntry {
     unsigned int slot;    // position of the query in cell order
     unsigned int count;   // |N(i)| before the cap
-    unsigned int cell;    // its (global) cell key
+    unsigned int pcell;   // packed coordinates of its cell
     unsigned int event;   // its event
 };
 
@@ -99,7 +108,7 @@ struct Workspace {
     Counters *ctr;
     Report *report;
     long long *edge_off;        // [n_events + 2] first edge of each event, then E, then a status
-    unsigned int *key;          // [rows] cell key of each point
+    unsigned int *pcell;        // [rows] packed cell coordinates of each point
     unsigned int *rank;         // [rows] arrival rank inside its cell
     unsigned int *cell_count;   // [cells] histogram
     unsigned int *cell_start;   // [cells + 1] exclusive scan of the histogram
@@ -107,7 +116,7 @@ struct Workspace {
     unsigned long long *sums_kept;   // [tiles of kPlaceTile rows] per-tile kept totals
     unsigned long long *sums_kept2;  // [groups of kKeptGroup tiles] per-group kept totals
     float *sorted;              // [rows, dpad] points in cell order, zero-padded rows
-    unsigned int *sorted_id;    // [2 rows] per sorted row: its original row, then its cell key
+    unsigned int *sorted_id;    // [2 rows] per sorted row: its original row, then its packed cell
     unsigned int *kept;         // [rows] neighbours kept per original row
     unsigned long long *tpos;   // [rows] where each query's list sits in `temp`
     HeavyEntry *heavy;          // [rows]
@@ -137,7 +146,8 @@ struct LaunchArgs {
     int max_n;          // rows of the largest event
     int d;
     int dpad;
-    int dims[3];
+    int axes;           // binned coordinates (3 or 4)
+    int dims[kMaxAxes]; // binned coordinates, axis 0 first (unused entries -1)
     float r;
     float r2;
     int K;

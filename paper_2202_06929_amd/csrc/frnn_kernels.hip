@@ -121,6 +121,41 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
     return v;
 }
 
+// Cross-lane steps with DPP (GFX9 encodings): row_shr:n moves lane i - n of the
+// same 16-lane row into lane i (0 when that lane is in another row); row_bcast:15
+// gives the rows selected by the row mask lane 15 of the row before; row_bcast:31
+// gives them lane 31.  Rows the mask leaves out keep `old` (here 0).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ unsigned int dpp_move(unsigned int v) {
+    return static_cast<unsigned int>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROW_MASK, 0xf, true));
+}
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+// Inclusive prefix sum across the 64 lanes (a scan within each row of 16 lanes,
+// then the row totals carried into the rows after them).
+__device__ __forceinline__ unsigned int wave_scan_add(unsigned int x) {
+    x += dpp_move<kRowShr1>(x);
+    x += dpp_move<kRowShr2>(x);
+    x += dpp_move<kRowShr4>(x);
+    x += dpp_move<kRowShr8>(x);
+    x += dpp_move<kRowBcast15, 0xa>(x);
+    x += dpp_move<kRowBcast31, 0xc>(x);
+    return x;
+}
+
+// Inclusive prefix maximum across the 64 lanes (values >= 0).
+__device__ __forceinline__ unsigned int wave_scan_max(unsigned int x) {
+    x = max(x, dpp_move<kRowShr1>(x));
+    x = max(x, dpp_move<kRowShr2>(x));
+    x = max(x, dpp_move<kRowShr4>(x));
+    x = max(x, dpp_move<kRowShr8>(x));
+    x = max(x, dpp_move<kRowBcast15, 0xa>(x));
+    x = max(x, dpp_move<kRowBcast31, 0xc>(x));
+    return x;
+}
+
 // Sum over the block; every thread gets the total.
 __device__ unsigned long long block_sum(unsigned long long v, unsigned long long *scratch) {
     v = wave_sum(v);
@@ -146,21 +181,29 @@ __device__ unsigned long long block_exclusive_scan(unsigned long long v, unsigne
 
 // ------------------------------------------------------------------ bounds
 
+// Binned coordinates of an event, axis 0 first; -1 for an axis that is not binned.
+struct Dims {
+    int c[kMaxAxes];
+};
+
 struct BoundsAcc {
-    float mn[3] = {INFINITY, INFINITY, INFINITY};
-    float mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float mn[kMaxAxes] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    float mx[kMaxAxes] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
     int bad = 0;
-    __device__ __forceinline__ void add(float v, int col, int d0, int d1, int d2) {
+    __device__ __forceinline__ void add(float v, int col, const Dims &dd) {
         bad |= !__builtin_isfinite(v);
-        if (col == d0) { mn[0] = fminf(mn[0], v); mx[0] = fmaxf(mx[0], v); }
-        if (col == d1) { mn[1] = fminf(mn[1], v); mx[1] = fmaxf(mx[1], v); }
-        if (col == d2) { mn[2] = fminf(mn[2], v); mx[2] = fmaxf(mx[2], v); }
+#pragma unroll
+        for (int p = 0; p < kMaxAxes; ++p)
+            if (col == dd.c[p]) {
+                mn[p] = fminf(mn[p], v);
+                mx[p] = fmaxf(mx[p], v);
+            }
     }
 };
 
 // Grid (bounds blocks, n_events): block (b, e) folds a share of event e's rows.
 // The first blocks also clear the histogram, tile totals and counters of the call.
-__global__ __launch_bounds__(kBlock) void k_bounds(int d, int d0, int d1, int d2,
+__global__ __launch_bounds__(kBlock) void k_bounds(int d, Dims dd,
                                                    int vec4, EventDesc *__restrict__ ev, EventDesc ev0,
                                                    int ev_from_arg, BoundsPartial *__restrict__ part,
                                                    unsigned int *__restrict__ cell_count, long long cells,
@@ -204,32 +247,32 @@ __global__ __launch_bounds__(kBlock) void k_bounds(int d, int d0, int d1, int d2
             for (int u = 0; u < 4; ++u) x[u] = X4[v + u * static_cast<long long>(stride)];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                acc.add(x[u].x, col, d0, d1, d2);
-                acc.add(x[u].y, col + 1, d0, d1, d2);
-                acc.add(x[u].z, col + 2, d0, d1, d2);
-                acc.add(x[u].w, col + 3, d0, d1, d2);
+                acc.add(x[u].x, col, dd);
+                acc.add(x[u].y, col + 1, dd);
+                acc.add(x[u].z, col + 2, dd);
+                acc.add(x[u].w, col + 3, dd);
                 col = next_col(col, step);
             }
         }
         for (; v < nv; v += stride) {
             const float4 x = X4[v];
-            acc.add(x.x, col, d0, d1, d2);
-            acc.add(x.y, col + 1, d0, d1, d2);
-            acc.add(x.z, col + 2, d0, d1, d2);
-            acc.add(x.w, col + 3, d0, d1, d2);
+            acc.add(x.x, col, dd);
+            acc.add(x.y, col + 1, dd);
+            acc.add(x.z, col + 2, dd);
+            acc.add(x.w, col + 3, dd);
             col = next_col(col, step);
         }
     } else {
         const int step = stride % d;
         int col = tid % d;
         for (long long e = tid; e < total; e += stride) {
-            acc.add(Xe[e], col, d0, d1, d2);
+            acc.add(Xe[e], col, dd);
             col = next_col(col, step);
         }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < kMaxAxes; ++p) {
             acc.mn[p] = fminf(acc.mn[p], __shfl_xor(acc.mn[p], o));
             acc.mx[p] = fmaxf(acc.mx[p], __shfl_xor(acc.mx[p], o));
         }
@@ -238,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_bounds(int d, int d0, int d1, int d2
     __shared__ BoundsPartial sp[kWaves];
     if (lane_id() == 0) {
         BoundsPartial &p = sp[wave_id()];
-        for (int q = 0; q < 3; ++q) {
+        for (int q = 0; q < kMaxAxes; ++q) {
             p.mn[q] = acc.mn[q];
             p.mx[q] = acc.mx[q];
         }
@@ -248,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_bounds(int d, int d0, int d1, int d2
     if (threadIdx.x == 0) {
         BoundsPartial out = sp[0];
         for (int w = 1; w < kWaves; ++w) {
-            for (int p = 0; p < 3; ++p) {
+            for (int p = 0; p < kMaxAxes; ++p) {
                 out.mn[p] = fminf(out.mn[p], sp[w].mn[p]);
                 out.mx[p] = fmaxf(out.mx[p], sp[w].mx[p]);
             }
@@ -263,10 +306,11 @@ __global__ __launch_bounds__(kBlock) void k_bounds(int d, int d0, int d1, int d2
 
 // Wave 0 of a block folds the bounds partials and lane 0 derives the grid.
 // Every block derives the same plan from the same partials (min/max are exact).
+// Axes from `axes` on are not binned: one cell each.
 __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, float r,
-                            int cell_div, int cells_max, Plan *out) {
-    float mn[3] = {INFINITY, INFINITY, INFINITY};
-    float mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+                            int cell_div, int axes, int cells_max, Plan *out) {
+    float mn[kMaxAxes] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    float mx[kMaxAxes] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
     int bad = 0;
     // Every lane loads its (at most kBoundsBlocks / 64) partials before folding them.
     constexpr int kPartsPerLane = kBoundsBlocks / 64;
@@ -279,7 +323,7 @@ __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, 
 #pragma unroll
     for (int u = 0; u < kPartsPerLane; ++u) {
         if (lane_id() + 64 * u >= nparts) continue;
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < kMaxAxes; ++p) {
             mn[p] = fminf(mn[p], pb[u].mn[p]);
             mx[p] = fmaxf(mx[p], pb[u].mx[p]);
         }
@@ -287,7 +331,7 @@ __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, 
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < kMaxAxes; ++p) {
             mn[p] = fminf(mn[p], __shfl_xor(mn[p], o));
             mx[p] = fmaxf(mx[p], __shfl_xor(mx[p], o));
         }
@@ -298,48 +342,52 @@ __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, 
     // |x_p - y_p| < r exactly along every coordinate (partial sums never exceed D,
     // rounding is monotone); the 2^-10 margin absorbs the float32 rounding of the
     // key computation (at most 3 * 2^-24 * G cells per point, G <= 1024), so such
-    // a pair lands at most cell_div cells apart along every binned axis.
+    // a pair lands at most cell_div cells apart along every binned axis.  Larger
+    // cells only keep such pairs closer.
     const float cbase = (r * 1.0009765625f) / static_cast<float>(cell_div);
-    float c[3], ext[3];
-    int G[3];
+    const int axis_max = axes == 4 ? kGridAxisMax4 : kGridAxisMax3;
+    const float axis_soft = axes == 4 ? 250.0f : 1000.0f;
+    float c[kMaxAxes], ext[kMaxAxes];
+    int G[kMaxAxes];
     // An axis whose extent is not a finite float (no points, or max - min
-    // overflowing) gets a single cell: inv_c = 0 puts every point in cell 0.
-    bool single[3];
-    for (int p = 0; p < 3; ++p) {
+    // overflowing), or that is not binned, gets a single cell: inv_c = 0 puts
+    // every point in cell 0.
+    bool single[kMaxAxes];
+    for (int p = 0; p < kMaxAxes; ++p) {
         ext[p] = mx[p] - mn[p];
-        single[p] = !(ext[p] >= 0.0f && ext[p] <= FLT_MAX);
+        single[p] = p >= axes || !(ext[p] >= 0.0f && ext[p] <= FLT_MAX);
         if (!(mn[p] <= mx[p])) mn[p] = 0.0f;
         c[p] = cbase;
-        if (!single[p] && ext[p] / c[p] > 1000.0f) c[p] = ext[p] / 1000.0f;
+        if (!single[p] && ext[p] / c[p] > axis_soft) c[p] = ext[p] / axis_soft;
     }
     // Grow the cells until the grid fits cells_max (bounded: after 128 rounds of
     // x1.25 every finite extent spans one cell).
     for (int round = 0;; ++round) {
         long long total = 1;
-        for (int p = 0; p < 3; ++p) {
+        for (int p = 0; p < kMaxAxes; ++p) {
             float g = single[p] ? 1.0f : floorf(ext[p] / c[p]) + 1.0f;
-            if (!(g <= static_cast<float>(kGridAxisMax))) g = static_cast<float>(kGridAxisMax);
+            if (!(g <= static_cast<float>(axis_max))) g = static_cast<float>(axis_max);
             if (!(g >= 1.0f)) g = 1.0f;
             G[p] = static_cast<int>(g);
             total *= G[p];
         }
         if (total <= cells_max) break;
         if (round >= 128) {
-            for (int p = 0; p < 3; ++p) single[p] = true;
+            for (int p = 0; p < kMaxAxes; ++p) single[p] = true;
             continue;
         }
-        for (int p = 0; p < 3; ++p) c[p] *= 1.25f;
+        for (int p = 0; p < kMaxAxes; ++p) c[p] *= 1.25f;
     }
-    for (int p = 0; p < 3; ++p) {
-        out->lo[p] = mn[p];
+    for (int p = 0; p < kMaxAxes; ++p) {
+        out->lo[p] = p < axes ? mn[p] : 0.0f;
         out->c[p] = single[p] ? INFINITY : c[p];
         out->inv_c[p] = single[p] ? 0.0f : 1.0f / c[p];
         out->G[p] = G[p];
     }
-    out->n_cells = G[0] * G[1] * G[2];
+    out->n_cells = G[0] * G[1] * G[2] * G[3];
     out->reach = cell_div;
     out->abort = bad;
-    out->pad = 0;
+    out->axes = axes;
 }
 
 // Clamping is monotone and moves no coordinate by more than the clamp, so two
@@ -351,15 +399,35 @@ __device__ __forceinline__ int cell_coord(float x, float lo, float inv_c, int G)
     return static_cast<int>(q);
 }
 
-constexpr int kMaxCellTiles = ((1 << 22) + kScanTile - 1) / kScanTile + 2;
+// Cell coordinates of a point pack into one word (cell_bits per axis); the cell
+// key orders cells with axis 0 fastest, so the cells along axis 0 around a cell
+// are contiguous in cell order.
+__device__ __forceinline__ unsigned int pack_cell(const int (&u)[kMaxAxes], int axes) {
+    const int b = cell_bits(axes);
+    return static_cast<unsigned int>(u[0]) | static_cast<unsigned int>(u[1]) << b |
+           static_cast<unsigned int>(u[2]) << (2 * b) | static_cast<unsigned int>(u[3]) << (3 * b);
+}
+
+__device__ __forceinline__ void unpack_cell(unsigned int pc, int axes, int (&u)[kMaxAxes]) {
+    const int b = cell_bits(axes);
+    const unsigned int m = (1u << b) - 1u;
+#pragma unroll
+    for (int p = 0; p < kMaxAxes; ++p) u[p] = static_cast<int>((pc >> (p * b)) & m);
+}
+
+__device__ __forceinline__ unsigned int cell_key(const int (&u)[kMaxAxes], const Plan &P) {
+    return static_cast<unsigned int>(((u[3] * P.G[2] + u[2]) * P.G[1] + u[1]) * P.G[0] + u[0]);
+}
+
+constexpr int kMaxCellTiles = ((1 << 24) + kScanTile - 1) / kScanTile + 2;
 
 // Grid (blocks, n_events) of kKeysBlock threads: block 0 of event e derives and
-// stores its plan; every block computes keys of a share of the event's rows.
-__global__ __launch_bounds__(kKeysBlock) void k_keys(int d, int d0, int d1, int d2,
+// stores its plan; every block computes the cells of a share of the event's rows.
+__global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
                                                      float r, int cell_div, const EventDesc *__restrict__ ev,
                                                      const BoundsPartial *__restrict__ part, int nparts,
                                                      Plan *__restrict__ plans, Counters *__restrict__ ctr,
-                                                     unsigned int *__restrict__ key,
+                                                     unsigned int *__restrict__ pcell,
                                                      unsigned int *__restrict__ rank,
                                                      unsigned int *__restrict__ cell_count,
                                                      unsigned long long *__restrict__ sums_cells) {
@@ -372,14 +440,15 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, int d0, int d1, int 
     // derived so that the two latencies overlap.
     const int i = blockIdx.x * kKeysBlock + threadIdx.x;
     const bool live = i < E.n;
-    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    float x[kMaxAxes] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (live) {
         const float *row = E.pts + static_cast<size_t>(i) * d;
-        x0 = row[d0];
-        x1 = row[d1];
-        x2 = row[d2];
+#pragma unroll
+        for (int p = 0; p < kMaxAxes; ++p)
+            if (p < axes) x[p] = row[dd.c[p]];
     }
-    if (wave_id() == 0) derive_plan(part + static_cast<size_t>(e) * nparts, nparts, r, cell_div, E.cells_max, &P);
+    if (wave_id() == 0)
+        derive_plan(part + static_cast<size_t>(e) * nparts, nparts, r, cell_div, axes, E.cells_max, &P);
     const int tile_end = static_cast<int>((E.cell0 + E.cells_max - 1) / kScanTile);
     const int ntiles = tile_end - E.tile0 + 1;
     for (int t = threadIdx.x; t < ntiles; t += kKeysBlock) tile_count[t] = 0u;
@@ -391,12 +460,11 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, int d0, int d1, int 
     if (P.abort) return;
     if (live) {
         const long long gi = E.row0 + i;
-        const int u0 = cell_coord(x0, P.lo[0], P.inv_c[0], P.G[0]);
-        const int u1 = cell_coord(x1, P.lo[1], P.inv_c[1], P.G[1]);
-        const int u2 = cell_coord(x2, P.lo[2], P.inv_c[2], P.G[2]);
-        const unsigned int k = static_cast<unsigned int>(E.cell0) +
-                               static_cast<unsigned int>((u2 * P.G[1] + u1) * P.G[0] + u0);
-        key[gi] = k;
+        int u[kMaxAxes];
+#pragma unroll
+        for (int p = 0; p < kMaxAxes; ++p) u[p] = cell_coord(x[p], P.lo[p], P.inv_c[p], P.G[p]);
+        const unsigned int k = static_cast<unsigned int>(E.cell0) + cell_key(u, P);
+        pcell[gi] = pack_cell(u, axes);
         rank[gi] = atomicAdd(&cell_count[k], 1u);
         atomicAdd(&tile_count[k / kScanTile - E.tile0], 1u);
     }
@@ -443,7 +511,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__res
 // Grid (blocks, n_events): block (b, e) copies a share of event e's rows.
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const EventDesc *__restrict__ ev,
-                                                    const unsigned int *__restrict__ key,
+                                                    const Plan *__restrict__ plans,
+                                                    const unsigned int *__restrict__ pcell,
                                                     const unsigned int *__restrict__ rank,
                                                     const unsigned int *__restrict__ cell_start,
                                                     const Counters *__restrict__ ctr,
@@ -451,10 +520,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
                                                     unsigned int *__restrict__ sorted_id) {
     if (ctr->abort) return;
     const EventDesc E = ev[blockIdx.y];
+    const Plan P = plans[blockIdx.y];
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < E.n; i += gridDim.x * kBlock) {
         const long long gi = E.row0 + i;
-        const unsigned int ck = key[gi];
-        const unsigned int slot = cell_start[ck] + rank[gi];
+        const unsigned int pc = pcell[gi];
+        int u[kMaxAxes];
+        unpack_cell(pc, P.axes, u);
+        const unsigned int slot = cell_start[static_cast<unsigned int>(E.cell0) + cell_key(u, P)] + rank[gi];
         float row[DP];
         if (vec4) {
             const float4 *src = reinterpret_cast<const float4 *>(E.pts + static_cast<size_t>(i) * d);
@@ -476,9 +548,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
 #pragma unroll
         for (int k = 0; k < DP / 4; ++k)
             out[k] = make_float4(row[4 * k], row[4 * k + 1], row[4 * k + 2], row[4 * k + 3]);
-        // The original row and the cell key of a sorted row sit side by side, so the
-        // scattered write is one 8-byte store instead of two 4-byte ones.
-        reinterpret_cast<uint2 *>(sorted_id)[slot] = make_uint2(static_cast<unsigned int>(gi), ck);
+        // The original row and the packed cell of a sorted row sit side by side, so
+        // the scattered write is one 8-byte store instead of two 4-byte ones.
+        reinterpret_cast<uint2 *>(sorted_id)[slot] = make_uint2(static_cast<unsigned int>(gi), pc);
     }
 }
 
@@ -496,35 +568,52 @@ __device__ __forceinline__ int find_event(const EventDesc *__restrict__ ev, int 
     return lo;
 }
 
-// The neighbour cells of local cell `cell` (global keys start at cell0) form (2R+1)^2 runs that are contiguous in cell
-// order (x is the fastest axis).  Lane t < (2R+1)^2 builds run t: its first sorted
-// row (start) and the number of candidate rows before it (pre).  Returns the
-// candidate count, the same in every lane.  Call with the whole wave active.
-__device__ __forceinline__ unsigned int wave_runs(unsigned int cell, unsigned int cell0, const Plan &P,
-                                                  const unsigned int *__restrict__ cell_start,
-                                                  unsigned int &start, unsigned int &pre) {
-    const int G0 = P.G[0], G1 = P.G[1], G2 = P.G[2];
-    const int ux = static_cast<int>(cell % static_cast<unsigned int>(G0));
-    const int uy = static_cast<int>((cell / static_cast<unsigned int>(G0)) % static_cast<unsigned int>(G1));
-    const int uz = static_cast<int>(cell / static_cast<unsigned int>(G0 * G1));
+// The neighbour cells of a cell are the cells at most R = reach cells away along
+// every binned axis.  Along axis 0 (the fastest in cell order) each group of them
+// is contiguous, so they form (2R+1)^(axes-1) runs of candidate rows.
+__device__ __forceinline__ int run_count(const Plan &P) {
+    const int side = 2 * P.reach + 1;
+    return P.axes == 4 ? side * side * side : side * side;
+}
+
+// Offsets along axes 1..3 of the run a lane builds (lanes below run_count).
+struct RunLane {
+    int a[3];
+    bool live;
+};
+
+__device__ __forceinline__ RunLane run_lane(const Plan &P) {
+    const int R = P.reach, side = 2 * R + 1, t = lane_id();
+    RunLane rl;
+    rl.live = t < run_count(P);
+    rl.a[0] = t % side - R;
+    rl.a[1] = (t / side) % side - R;
+    rl.a[2] = P.axes == 4 ? t / (side * side) - R : 0;
+    return rl;
+}
+
+// Lane t < run_count builds run t around the cell with coordinates u (global keys
+// start at cell0): its first sorted row (start) and its candidates [pre, end) in
+// the tile's candidate numbering (other lanes: an empty run at the end).  Returns
+// the candidate count, the same in every lane.  Call with the whole wave active.
+__device__ __forceinline__ unsigned int wave_runs(const int (&u)[kMaxAxes], unsigned int cell0, const Plan &P,
+                                                  const RunLane &rl, const unsigned int *__restrict__ cell_start,
+                                                  unsigned int &start, unsigned int &pre, unsigned int &end) {
     const int R = P.reach;
-    const int side = 2 * R + 1;
-    const int t = lane_id();
     unsigned int len = 0;
     start = 0;
-    if (t < side * side) {
-        const int yy = uy + (t % side) - R;
-        const int zz = uz + (t / side) - R;
-        if (yy >= 0 && yy < G1 && zz >= 0 && zz < G2) {
-            const int xlo = max(ux - R, 0), xhi = min(ux + R, G0 - 1);
-            const unsigned int row = cell0 + static_cast<unsigned int>((zz * G1 + yy) * G0);
+    if (rl.live) {
+        const int y = u[1] + rl.a[0], z = u[2] + rl.a[1], w = u[3] + rl.a[2];
+        if (y >= 0 && y < P.G[1] && z >= 0 && z < P.G[2] && w >= 0 && w < P.G[3]) {
+            const int xlo = max(u[0] - R, 0), xhi = min(u[0] + R, P.G[0] - 1);
+            const unsigned int row = cell0 + static_cast<unsigned int>(((w * P.G[2] + z) * P.G[1] + y) * P.G[0]);
             start = cell_start[row + xlo];
             len = cell_start[row + xhi + 1] - start;
         }
     }
-    const unsigned int inc = wave_inclusive_scan(len);
-    pre = inc - len;
-    return uniform(static_cast<unsigned int>(__shfl(inc, 63)));
+    end = wave_scan_add(len);
+    pre = end - len;
+    return __builtin_amdgcn_readlane(end, 63);
 }
 
 // ------------------------------------------------------------------ search
@@ -566,6 +655,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     // lane-addressed entries: (q << 6 | lane) << 32 | bits of the partial sum.
     __shared__ unsigned long long ring_all[kWaves][kRing];
     __shared__ float racc_all[DP <= 8 ? kWaves : 1][DP <= 8 ? kRing : 1];
+    __shared__ unsigned int mark_all[kWaves][64];  // run starting at each lane of a chunk, plus one
     __shared__ unsigned long long tested_w[kWaves];
     __shared__ unsigned long long survived_w[kWaves];
     __shared__ unsigned int capped_w[kWaves];
@@ -579,8 +669,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned int *qcnt = qcnt_all[wave_id()];
     unsigned long long *ring = ring_all[wave_id()];
     float *racc = racc_all[DP <= 8 ? wave_id() : 0];
+    unsigned int *mark = mark_all[wave_id()];
     const int lane = lane_id();
-    const unsigned int total_waves = gridDim.x * kWaves;
     // Terms before the first exact rejection test: two for rows of up to 8 floats
     // (their three-term test rejects few more pairs than two terms do, and the
     // first stage runs for every query and candidate), four for 12-float rows
@@ -591,8 +681,12 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     // remaining coordinates are loaded when the entry is finished) for rows of up to
     // 8 floats; wider rows exchange the candidate's coordinates between lanes instead.
     constexpr bool kRowRing = DP <= 8;
+    // Pairs examined (lane q counts those of query q of each group) and pairs that
+    // reached the second stage (each lane counts those it queued).  Per-lane counts
+    // in vector registers, summed once at the end: scalar registers are the scarce
+    // ones in this kernel.
     unsigned long long tested = 0;
-    unsigned long long survived = 0;  // pairs that reached the second stage
+    unsigned long long survived = 0;
 
     // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
     // workgroups of one XCD take consecutive queries and share their rows in its L2.
@@ -610,24 +704,40 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     const unsigned int q_hi = q_lo + q_base + (gw < q_rem ? 1u : 0u);
     int ev_cur = -1;
     Plan P;
+    RunLane rl;
     unsigned int cell0 = 0;
-    int nruns = 1;
-    for (unsigned int qa = q_lo; qa < q_hi;) {
-        const unsigned int cell = uniform(sorted_id[2u * qa + 1u]);
-        const unsigned int qs = qa;
-        const unsigned int qe = min(uniform(cell_start[cell + 1]), q_hi);
-        qa = qe;
-        {
-            const int e = n_events == 1 ? 0 : find_event(ev, n_events, qs);
-            if (e != ev_cur) {
+    unsigned int ev_end = 0;  // first row after the current event
+    const uint2 *__restrict__ sid = reinterpret_cast<const uint2 *>(sorted_id);
+    // The share is read in windows of 64 queries: lane l holds query win + l (its
+    // original row and packed cell), and a tile is a run of consecutive lanes with the
+    // same cell, found by a ballot (no per-tile lookup of where the cell ends).
+    for (unsigned int win = q_lo; win < q_hi;) {
+        const unsigned int nwin = min(64u, q_hi - win);
+        uint2 me = make_uint2(0u, 0u);
+        if (static_cast<unsigned int>(lane) < nwin) me = sid[win + lane];
+        const unsigned int v_orig = me.x, v_pc = me.y;
+        for (unsigned int t0 = 0; t0 < nwin;) {
+            const unsigned int qs = win + t0;
+            if (qs >= ev_end) {
+                const int e = n_events == 1 ? 0 : find_event(ev, n_events, qs);
                 ev_cur = e;
                 P = plans[e];
-                cell0 = static_cast<unsigned int>(ev[e].cell0);
-                const int side = 2 * P.reach + 1;
-                nruns = side * side;
+                const EventDesc E = ev[e];
+                cell0 = static_cast<unsigned int>(E.cell0);
+                ev_end = static_cast<unsigned int>(E.row0) + static_cast<unsigned int>(E.n);
+                rl = run_lane(P);
             }
-            unsigned int start, pre;
-            const unsigned int M = wave_runs(cell - cell0, cell0, P, cell_start, start, pre);
+            const unsigned int pc = __builtin_amdgcn_readlane(v_pc, t0);
+            const unsigned long long other =
+                __builtin_amdgcn_ballot_w64(static_cast<unsigned int>(lane) >= nwin || v_pc != pc) &
+                (~0ull << t0);
+            unsigned int t1 = other ? static_cast<unsigned int>(__builtin_ctzll(other)) : 64u;
+            t1 = min(t1, ev_end - win);  // a tile never crosses into the next event
+            const unsigned int qe = win + t1;
+            int u[kMaxAxes];
+            unpack_cell(pc, P.axes, u);
+            unsigned int start, pre, end;
+            const unsigned int M = wave_runs(u, cell0, P, rl, cell_start, start, pre, end);
             for (unsigned int q0 = qs; q0 < qe; q0 += kQT) {
                 const int Qn = static_cast<int>(uniform(min(static_cast<unsigned int>(kQT), qe - q0)));
                 if (prio) {
@@ -652,22 +762,20 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 constexpr int kHeld = kRowRing ? 4 : DP;  // candidate coordinates held per lane
                 float cn[kHeld];
                 unsigned int sn, jn = 0u;
-                // rc: the run holding candidate b (wave-uniform).  Runs are consecutive
-                // ranges of candidates, so only the runs that start inside the chunk
-                // need to be compared with each lane's candidate number.
-                int rc = 0;
+                // Candidate b + lane lies in the last run that starts at or before it:
+                // each run that starts inside the chunk marks its first lane (the run
+                // holding candidate b marks lane 0) and a prefix maximum spreads the
+                // marks over the lanes after them.
                 auto fetch = [&](unsigned int b) {
-                    while (rc + 1 < nruns && __builtin_amdgcn_readlane(pre, rc + 1) <= b) ++rc;
+                    wave_lds_sync();
+                    mark[lane] = 0u;
+                    wave_lds_sync();
+                    if (end > pre && pre < b + 64u && end > b) mark[pre > b ? pre - b : 0u] = lane + 1u;
+                    wave_lds_sync();
+                    const int r = static_cast<int>(wave_scan_max(mark[lane])) - 1;
                     const unsigned int mm = b + lane;
-                    const unsigned int m = mm < M ? mm : b;
-                    int r = rc;
-                    for (int t = rc + 1; t < nruns; ++t) {
-                        const unsigned int p = __builtin_amdgcn_readlane(pre, t);
-                        if (p >= b + 64u) break;
-                        r += m >= p ? 1 : 0;
-                    }
                     const unsigned int srow = static_cast<unsigned int>(__shfl(start, r)) +
-                                              (m - static_cast<unsigned int>(__shfl(pre, r)));
+                                              (mm - static_cast<unsigned int>(__shfl(pre, r)));
                     sn = mm < M ? srow : 0u;
                     if constexpr (kRowRing) {
                         const float4 v = *reinterpret_cast<const float4 *>(sorted + static_cast<size_t>(sn) * DP);
@@ -765,6 +873,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2);
                         if (m1 == 0ull) continue;
                         if (acc < r2) {
+                            ++survived;
                             const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
                             if constexpr (kRowRing) {
                                 ring[e] = (static_cast<unsigned long long>(uniform(static_cast<unsigned int>(q))) << 32) | s;
@@ -791,8 +900,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     if (tail != head) finish_rows(head, tail - head);
                 }
                 const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
-                tested += static_cast<unsigned long long>(Qn) * M;
-                survived += tail;
+                if (lane < Qn) tested += M;
+                // Original row of query q0 + lane, held by lane q0 + lane - win.
+                const unsigned int iq = static_cast<unsigned int>(
+                    __shfl(static_cast<int>(v_orig), static_cast<int>((q0 - win + lane) & 63u)));
                 wave_lds_sync();
                 // Kept counts for every query; lists that fit are stored at a fixed place
                 // (kListCap slots per sorted row), longer ones go to the long-list kernel.
@@ -800,7 +911,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                   (SEL || cnt <= static_cast<unsigned int>(K));
                 if (lane < Qn) {
                     const unsigned int slot = q0 + lane;
-                    const unsigned int i = sorted_id[2u * slot];
+                    const unsigned int i = iq;
                     kept[i] = min(cnt, static_cast<unsigned int>(K));
                     if (cnt > static_cast<unsigned int>(K)) ++capped;
                     if (fits) {
@@ -810,7 +921,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         HeavyEntry he;
                         he.slot = slot;
                         he.count = cnt;
-                        he.cell = cell;
+                        he.pcell = pc;
                         he.event = static_cast<unsigned int>(ev_cur);
                         heavy[h] = he;
                     }
@@ -885,9 +996,13 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 }
                 wave_lds_sync();
             }
+            t0 = t1;
         }
+        win += nwin;
     }
     capped = wave_sum(capped);
+    tested = wave_sum(tested);
+    survived = wave_sum(survived);
     if (lane == 0) {
         tested_w[wave_id()] = tested;
         survived_w[wave_id()] = survived;
@@ -934,7 +1049,6 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
     __shared__ unsigned int fill_s;
     __shared__ unsigned long long prefix_s, base_s;
     __shared__ unsigned int remaining_s;
-    __shared__ unsigned long long scratch[kWaves];
 
     if (ctr->abort) return;
 
@@ -963,12 +1077,13 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
         const HeavyEntry he = heavy[h];
         const Plan P = plans[he.event];
         const unsigned int cell0 = static_cast<unsigned int>(ev[he.event].cell0);
-        const int side = 2 * P.reach + 1;
-        const int nruns = side * side;
+        const int nruns = run_count(P);
         for (int k = threadIdx.x; k < DP; k += kBlock) qv[k] = sorted[static_cast<size_t>(he.slot) * DP + k];
         if (wave_id() == 0) {
-            unsigned int start, pre;
-            const unsigned int M = wave_runs(he.cell - cell0, cell0, P, cell_start, start, pre);
+            int u[kMaxAxes];
+            unpack_cell(he.pcell, P.axes, u);
+            unsigned int start, pre, end;
+            const unsigned int M = wave_runs(u, cell0, P, run_lane(P), cell_start, start, pre, end);
             run_start[lane_id()] = start;
             run_pre[lane_id()] = pre;
             if (lane_id() == 0) run_pre[64] = M;
@@ -1150,7 +1265,7 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
             rep.capped = static_cast<unsigned int>(cp);
             rep.heavy = ctr->heavy_count;
             rep.n_cells = P.n_cells;
-            for (int p = 0; p < 3; ++p) {
+            for (int p = 0; p < kMaxAxes; ++p) {
                 rep.G[p] = P.G[p];
                 rep.c[p] = P.c[p];
             }
@@ -1271,8 +1386,8 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     const long long rows = ws.rows;
     const long long nb = (static_cast<long long>(a.max_n) + kBlock - 1) / kBlock;
     const int gs = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
-    hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, ws.key,
-                       ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id);
+    hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, ws.plans,
+                       ws.pcell, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id);
     mark(4);
     const unsigned int sq_base = static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves));
     const unsigned int sq_rem = static_cast<unsigned int>(rows % (static_cast<long long>(a.search_blocks) * kWaves));
@@ -1332,14 +1447,16 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
     const int vec4 = a.vec4;
     const long long kb = (static_cast<long long>(a.max_n) + kKeysBlock - 1) / kKeysBlock;
     const int gkeys = static_cast<int>(kb < 1 ? 1 : kb);  // one point per thread
+    Dims dd;
+    for (int p = 0; p < kMaxAxes; ++p) dd.c[p] = p < a.axes ? a.dims[p] : -1;
     mark(0);
-    hipLaunchKernelGGL(k_bounds, dim3(a.bounds_blocks, a.n_events), dim3(kBlock), 0, a.stream, a.d,
-                       a.dims[0], a.dims[1], a.dims[2], vec4, ws.ev, a.ev0, a.ev_from_arg, ws.part, ws.cell_count,
-                       ws.cells, ws.sums_cells, ws.tiles_cells_n, ws.sums_kept2, ws.groups_kept_n, ws.ctr);
+    hipLaunchKernelGGL(k_bounds, dim3(a.bounds_blocks, a.n_events), dim3(kBlock), 0, a.stream, a.d, dd, vec4,
+                       ws.ev, a.ev0, a.ev_from_arg, ws.part, ws.cell_count, ws.cells, ws.sums_cells,
+                       ws.tiles_cells_n, ws.sums_kept2, ws.groups_kept_n, ws.ctr);
     mark(1);
-    hipLaunchKernelGGL(k_keys, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.d, a.dims[0],
-                       a.dims[1], a.dims[2], a.r, a.cell_div, ws.ev, ws.part, a.bounds_blocks, ws.plans, ws.ctr, ws.key,
-                       ws.rank, ws.cell_count, ws.sums_cells);
+    hipLaunchKernelGGL(k_keys, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.d, dd, a.axes, a.r,
+                       a.cell_div, ws.ev, ws.part, a.bounds_blocks, ws.plans, ws.ctr, ws.pcell, ws.rank,
+                       ws.cell_count, ws.sums_cells);
     mark(2);
     hipLaunchKernelGGL(k_scan_tiles<unsigned int>, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream,
                        ws.cell_count, ws.cells, ws.sums_cells, ws.cell_start);

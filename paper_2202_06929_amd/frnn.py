@@ -37,20 +37,21 @@ class FrnnError(RuntimeError):
 
 
 class FrnnConfig(ctypes.Structure):
-    _fields_ = [("dims", ctypes.c_int32 * 3), ("cell_div", ctypes.c_int32),
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("axes", ctypes.c_int32), ("cell_div", ctypes.c_int32),
                 ("grid_mult", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class FrnnStats(ctypes.Structure):
     _fields_ = [("n_edges", ctypes.c_int64), ("candidates", ctypes.c_int64),
-                ("n_cells", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
-                ("dims", ctypes.c_int32 * 3), ("cell", ctypes.c_float * 3),
+                ("n_cells", ctypes.c_int64), ("axes", ctypes.c_int32), ("grid", ctypes.c_int32 * 4),
+                ("dims", ctypes.c_int32 * 4), ("cell", ctypes.c_float * 4),
                 ("capped_queries", ctypes.c_int32), ("overflow_queries", ctypes.c_int32),
                 ("stage_ms", ctypes.c_float * 7), ("survivors", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
+        a = self.axes
         return {"n_edges": self.n_edges, "candidates": self.candidates, "n_cells": self.n_cells,
-                "grid": list(self.grid), "dims": list(self.dims), "cell": list(self.cell),
+                "axes": a, "grid": list(self.grid)[:a], "dims": list(self.dims)[:a], "cell": list(self.cell)[:a],
                 "capped_queries": self.capped_queries, "overflow_queries": self.overflow_queries,
                 "stage_ms": dict(zip(STAGES, self.stage_ms)), "survivors": self.survivors}
 
@@ -59,7 +60,8 @@ class FrnnStats(ctypes.Structure):
 class Config:
     """Speed-only tunables; every choice yields the same edges."""
 
-    dims: tuple[int, int, int] | None = None  # binned coordinates (default: the last three)
+    dims: tuple[int, ...] | None = None         # 3 or 4 binned coordinates (default: the last ones)
+    axes: int = 0                               # binned count when dims is None (0: automatic)
     cell_div: int = 1                           # cell edge = r (1 + 2^-10) / cell_div
     grid_mult: int = 0                          # search workgroups per resident slot (0: automatic)
     timing: bool = False                        # per-stage HIP event timing in the stats
@@ -67,9 +69,13 @@ class Config:
 
     def to_c(self) -> FrnnConfig:
         c = FrnnConfig()
+        c.axes = int(self.axes)
         if self.dims is not None:
-            for p in range(3):
-                c.dims[p] = int(self.dims[p])
+            if len(self.dims) not in (3, 4):
+                raise ValueError("dims must name 3 or 4 coordinates")
+            for p, v in enumerate(self.dims):
+                c.dims[p] = int(v)
+            c.axes = len(self.dims)
         c.cell_div = int(self.cell_div)
         c.grid_mult = int(self.grid_mult)
         c.flags = (FLAG_TIMING if self.timing else 0) | (FLAG_EVENTS_RESIDENT if self.events_resident else 0)

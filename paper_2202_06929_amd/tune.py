@@ -1,6 +1,6 @@
-"""Autotuner of the grid search: picks the cell size, the binned coordinates and the
-search grid (workgroups per resident slot) for a workload by timing each candidate
-on a sample batch.
+"""Autotuner of the grid search: picks the cell size, the binned coordinates (three
+or four, and which) and the search grid (workgroups per resident slot) for a
+workload by timing each candidate on a sample batch.
 
 Every candidate must return byte-identical edges (they are speed-only choices of
 the same exact search); the tuner checks that on the device and refuses to pick
@@ -10,6 +10,7 @@ bucket, r, K), so a workload is tuned once per machine.
 
 from __future__ import annotations
 
+import dataclasses
 import json
 import math
 import os
@@ -24,22 +25,31 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "frnn_mi355x_tun
 
 
 def candidates(d: int) -> list[frnn.Config]:
-    """Cell divisions 1-3 crossed with three choices of binned coordinates: the last
+    """Four binned coordinates (when d >= 5: the last four, and for d >= 8 a spread
+    of four), then three binned coordinates crossed with cell divisions 1-3: the last
     three (leading terms of the distance sum unbinned, so the early exit bites), the
     first three, and a spread of coordinates.  The search grid is then tuned for the
     best of these (grid_candidates)."""
+    out = []
+    if d >= 5:
+        out.append(frnn.Config(axes=4))
+    if d >= 8:
+        out.append(frnn.Config(dims=(d // 2 - 1, d // 2, d // 2 + 1, d - 1)))
     dim_sets = [None, (0, 1, 2)]
     if d >= 6:
         dim_sets.append((d // 2, d // 2 + 1, d - 1))
-    out = []
     for dims in dim_sets:
         for div in (1, 2, 3):
-            out.append(frnn.Config(dims=dims, cell_div=div))
+            out.append(frnn.Config(dims=dims, axes=3 if dims is None else 0, cell_div=div))
     return out
 
 
 def grid_candidates(best: frnn.Config) -> list[frnn.Config]:
-    return [frnn.Config(dims=best.dims, cell_div=best.cell_div, grid_mult=m) for m in (1, 2, 4)]
+    return [dataclasses.replace(best, grid_mult=m) for m in (1, 2, 4)]
+
+
+def describe(cfg: frnn.Config) -> str:
+    return f"dims={cfg.dims} axes={cfg.axes} div={cfg.cell_div} grid={cfg.grid_mult}"
 
 
 def size_bucket(rows: int) -> int:
@@ -73,8 +83,8 @@ def tune(points: torch.Tensor, offsets, r: float, K: int, repeats: int = 5,
             cache = json.load(f)
         if key in cache:
             c = cache[key]
-            return frnn.Config(dims=tuple(c["dims"]) if c["dims"] else None, cell_div=c["cell_div"],
-                               grid_mult=c.get("grid_mult", 0)), c
+            return frnn.Config(dims=tuple(c["dims"]) if c["dims"] else None, axes=c.get("axes", 0),
+                               cell_div=c["cell_div"], grid_mult=c.get("grid_mult", 0)), c
     first = cands or candidates(d)
     _, eo0 = frnn.build_batch(points, off, r, K, config=first[0])
     cap = int(eo0[-1]) + 1024
@@ -109,9 +119,9 @@ def tune(points: torch.Tensor, offsets, r: float, K: int, repeats: int = 5,
     if not cands:
         run(grid_candidates(min(timings, key=timings.get)))
     best = min(timings, key=timings.get)
-    report = {"dims": list(best.dims) if best.dims else None, "cell_div": best.cell_div,
+    report = {"dims": list(best.dims) if best.dims else None, "axes": best.axes, "cell_div": best.cell_div,
               "grid_mult": best.grid_mult, "seconds": timings[best], "key": key,
-              "all": {f"dims={c.dims} div={c.cell_div} grid={c.grid_mult}": t for c, t in timings.items()}}
+              "all": {describe(c): t for c, t in timings.items()}}
     if cache_path:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         cache = {}

@@ -19,7 +19,7 @@ def declared_functions():
 
 def test_header_compiles_as_c_and_cxx(tmp_path):
     src = tmp_path / "use.c"
-    src.write_text('#include "frnn.h"\nint main(void) { frnn_config c = {{0, 0, 0}, 0, 0, 0}; frnn_stats s; (void)c; (void)s; return FRNN_OK; }\n')
+    src.write_text('#include "frnn.h"\nint main(void) { frnn_config c = {{0, 0, 0, 0}, 0, 0, 0, 0}; frnn_stats s; (void)c; (void)s; return FRNN_OK; }\n')
     for std, lang in (("-std=c99", "c"), ("-std=c++17", "c++")):
         subprocess.run(["gcc" if lang == "c" else "g++", std, "-Wall", "-Wextra", "-pedantic", "-Werror",
                         "-fsyntax-only", "-x", lang, f"-I{os.path.dirname(HEADER)}", str(src)], check=True)
@@ -93,6 +93,20 @@ def test_argument_errors_return_before_touching_a_device(lib):
     bad = frnn.FrnnConfig()
     bad.cell_div = 4
     assert _call(lib, cfg=bad)[0] == ERR
+    for axes in (1, 2, 5, -1):
+        bad = frnn.FrnnConfig()
+        bad.axes = axes
+        assert _call(lib, cfg=bad)[0] == ERR
+    bad = frnn.FrnnConfig()
+    bad.axes, bad.cell_div = 4, 2                 # four binned coordinates need cell_div 1
+    assert _call(lib, cfg=bad)[0] == ERR
+    bad = frnn.FrnnConfig()
+    bad.axes = 4
+    assert _call(lib, d=3, cfg=bad)[0] == ERR    # more binned coordinates than d
+    bad.dims[0], bad.dims[1], bad.dims[2], bad.dims[3] = 0, 1, 2, 1
+    assert _call(lib, cfg=bad)[0] == ERR         # repeated coordinate
+    bad.dims[3] = 8
+    assert _call(lib, cfg=bad)[0] == ERR         # coordinate out of range
     bad = frnn.FrnnConfig()
     bad.grid_mult = 3
     assert _call(lib, cfg=bad)[0] == ERR

@@ -78,15 +78,33 @@ def test_every_dimension_bucket(d):
 
 
 @pytest.mark.parametrize("cfg", [
-    frnn.Config(), frnn.Config(dims=(0, 1, 2)), frnn.Config(dims=(2, 0, 5)),
+    frnn.Config(), frnn.Config(axes=3), frnn.Config(dims=(0, 1, 2)), frnn.Config(dims=(2, 0, 5)),
+    frnn.Config(dims=(0, 1, 2, 3)), frnn.Config(dims=(6, 0, 3, 5)),
     frnn.Config(cell_div=2), frnn.Config(cell_div=3), frnn.Config(dims=(0, 1, 2), cell_div=2),
-    frnn.Config(grid_mult=1), frnn.Config(grid_mult=8),
-], ids=["default", "lead_dims", "mixed_dims", "div2", "div3", "lead_div2", "grid1", "grid8"])
+    frnn.Config(grid_mult=1), frnn.Config(grid_mult=8), frnn.Config(axes=3, grid_mult=8),
+], ids=["default", "three_axes", "lead_dims", "mixed_dims", "lead_dims4", "mixed_dims4", "div2", "div3",
+        "lead_div2", "grid1", "grid8", "three_axes_grid8"])
 @pytest.mark.parametrize("name", ["tiny", "single"])
 def test_every_config_gives_the_same_edges(cfg, name):
     spec, X, want = event_and_oracle(name)
     log(f"config {cfg} on {name}")
     assert_same(gpu_edges(X, spec.r, spec.K, config=cfg), want)
+
+
+@pytest.mark.parametrize("d", [4, 5])
+def test_four_axes_on_few_coordinates(d):
+    """Four binned coordinates when d is 4 (every coordinate binned, so the
+    leading terms of the sum are binned too) and 5."""
+    spec = events.EventSpec(n=4000, d=d, n_clusters=300, size_lo=5, size_hi=15, sigma=0.02,
+                            noise_frac=0.1, r=0.1, K=32, seed=60 + d)
+    X, _ = events.generate(spec)
+    log(f"four axes, d={d}")
+    want = oracle.frnn_grid(X, spec.r, spec.K)
+    got, st = frnn.build(torch.from_numpy(X).to(DEV), spec.r, spec.K, config=frnn.Config(axes=4),
+                         return_stats=True)
+    torch.cuda.synchronize()
+    assert st["axes"] == 4 and st["dims"] == list(range(d - 4, d))
+    assert_same(got.cpu().numpy(), want)
 
 
 def test_repeated_runs_are_identical():
@@ -282,6 +300,8 @@ def test_small_caps_on_dense_cells(d, K):
     want = oracle.frnn_grid(X, 0.1, K)
     assert_same(gpu_edges(X, 0.1, K), want)
     assert_same(gpu_edges(X, 0.1, K, config=frnn.Config(dims=(0, 1, 2))), want)
+    if d >= 4:
+        assert_same(gpu_edges(X, 0.1, K, config=frnn.Config(dims=(0, 1, 2, 3))), want)
 
 
 def test_nearest_eight_on_the_single_event():
@@ -337,15 +357,15 @@ def benchmark_batch():
     return sizes, evs, _oracle_many(evs, 0.1, 256)
 
 
-@pytest.mark.parametrize("grid_mult", [0, 4])
-def test_benchmark_batch_of_64_events(grid_mult):
-    """The benchmark's batch (64 events of 20k-150k hits, binned coordinates 4, 5, 7
-    as the tuner picks them): every event equals the oracle's edges of that event."""
+@pytest.mark.parametrize("cfg", [frnn.Config(), frnn.Config(grid_mult=4), frnn.Config(dims=(4, 5, 7))],
+                         ids=["default", "grid4", "three_axes_457"])
+def test_benchmark_batch_of_64_events(cfg):
+    """The benchmark's batch (64 events of 20k-150k hits): every event equals the
+    oracle's edges of that event, with four binned coordinates and with three."""
     sizes, evs, want = benchmark_batch()
     offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     pts = torch.from_numpy(np.concatenate(evs)).to(DEV)
-    cfg = frnn.Config(dims=(4, 5, 7), grid_mult=grid_mult)
-    log(f"benchmark batch: {offsets[-1]} rows, grid_mult {grid_mult}")
+    log(f"benchmark batch: {offsets[-1]} rows, {cfg}")
     edges, eo = frnn.build_batch(pts, offsets, 0.1, 256, cfg)
     edges = edges.cpu().numpy()
     assert eo[-1] == sum(w.shape[1] for w in want)

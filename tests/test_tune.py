@@ -74,7 +74,7 @@ def test_picks_the_fastest_config_then_tunes_its_grid(stub, tmp_path):
     assert len(report["all"]) == n_first + len(tune.grid_candidates(best))
     assert report["key"] == tune.cache_key("stub", 8, 1000, 0.1, 256)
     stored = json.load(open(cache))[report["key"]]
-    assert stored["dims"] == [0, 1, 2] and stored["cell_div"] == 2
+    assert stored["dims"] == [0, 1, 2] and stored["cell_div"] == 2 and stored["axes"] == 0
 
 
 def test_cache_hit_skips_timing_and_other_sizes_miss(stub, tmp_path):
