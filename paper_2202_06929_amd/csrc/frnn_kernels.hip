@@ -600,17 +600,20 @@ __device__ __forceinline__ unsigned int wave_runs(const int (&u)[kMaxAxes], unsi
                                                   const RunLane &rl, const unsigned int *__restrict__ cell_start,
                                                   unsigned int &start, unsigned int &pre, unsigned int &end) {
     const int R = P.reach;
-    unsigned int len = 0;
-    start = 0;
-    if (rl.live) {
-        const int y = u[1] + rl.a[0], z = u[2] + rl.a[1], w = u[3] + rl.a[2];
-        if (y >= 0 && y < P.G[1] && z >= 0 && z < P.G[2] && w >= 0 && w < P.G[3]) {
-            const int xlo = max(u[0] - R, 0), xhi = min(u[0] + R, P.G[0] - 1);
-            const unsigned int row = cell0 + static_cast<unsigned int>(((w * P.G[2] + z) * P.G[1] + y) * P.G[0]);
-            start = cell_start[row + xlo];
-            len = cell_start[row + xhi + 1] - start;
-        }
-    }
+    // Branch-free: every lane loads (a lane without a run reads the event's first
+    // row of cells, a valid address) and keeps its run only if it is inside the grid
+    // (the unsigned comparisons also reject negative coordinates).
+    const int y = u[1] + rl.a[0], z = u[2] + rl.a[1], w = u[3] + rl.a[2];
+    const bool ok = rl.live & (static_cast<unsigned int>(y) < static_cast<unsigned int>(P.G[1])) &
+                    (static_cast<unsigned int>(z) < static_cast<unsigned int>(P.G[2])) &
+                    (static_cast<unsigned int>(w) < static_cast<unsigned int>(P.G[3]));
+    const int xlo = max(u[0] - R, 0), xhi = min(u[0] + R, P.G[0] - 1);
+    const unsigned int row =
+        cell0 + (ok ? static_cast<unsigned int>(((w * P.G[2] + z) * P.G[1] + y) * P.G[0]) : 0u);
+    const unsigned int s0 = cell_start[row + xlo];
+    const unsigned int s1 = cell_start[row + xhi + 1];
+    start = ok ? s0 : 0u;
+    const unsigned int len = ok ? s1 - s0 : 0u;
     end = wave_scan_add(len);
     pre = end - len;
     return __builtin_amdgcn_readlane(end, 63);
