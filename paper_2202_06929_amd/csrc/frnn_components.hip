@@ -5,18 +5,17 @@
 // runs on the edge list that already exists).
 //
 // Lock-free union-find on a parent array (one 32-bit entry per vertex):
-//   k_cc_init   parent[v] = v
-//   k_cc_hook   one lane per kept edge: find both roots (plain reads: the only
-//               writes of this kernel are the hooks, device-scope atomics that are
-//               performed beyond the per-XCD caches and cost memory traffic), hook
-//               the larger root under the smaller one with a compare-and-swap,
-//               retry from the new roots if another thread hooked it first.
-//               Edges come grouped by source, so lanes of a wave often share the
-//               source's root; such a group is merged as a star around the
-//               smallest root in it (each lane hooks its own endpoint's root, one
-//               lane hooks the source's), which spreads the compare-and-swaps over
-//               distinct addresses instead of retrying on one
-//   k_cc_label  label[v] = root of v (path halving); counts the roots
+//   k_cc_init     parent[v] = v
+//   k_cc_minhook  each source hooked under its smallest neighbour (see there), so
+//                 that clusters whose vertices all neighbour their smallest vertex
+//                 are stars before the next pass
+//   k_cc_hook     one lane per kept edge: find both roots (plain reads: the only
+//                 writes of this kernel are the hooks, device-scope atomics that are
+//                 performed beyond the per-XCD caches and cost memory traffic), hook
+//                 the larger root under the smaller one with a compare-and-swap,
+//                 retry from the new roots if another thread hooked it first
+//   k_cc_label    label[v] = root of v (path halving); counts the roots; the last
+//                 workgroup writes the component count and the status
 // Parent pointers only ever point to smaller ids (hooks go from the larger root
 // to the smaller, halving jumps to an ancestor), so there are no cycles and every
 // find ends.  When all edges are done each component is one tree, and its root is
@@ -47,8 +46,17 @@ constexpr unsigned int kMaxHookRounds = 1u << 20;
 struct CcState {
     unsigned int status;             // bit 0: endpoint out of range; bit 1: hook bound reached
     unsigned int pad;
-    unsigned long long n_components;
+    // Labeling workgroups done (bits 44..63) and roots counted so far (bits 0..43),
+    // one word so that a single atomic add both counts and tells the last workgroup.
+    unsigned long long done_roots;
 };
+
+constexpr int kRootBits = 44;
+constexpr unsigned long long kRootMask = (1ull << kRootBits) - 1;
+
+__device__ __forceinline__ long long status_code(unsigned int s) {
+    return (s & 1u) ? FRNN_ERR_ARG : ((s & 2u) ? FRNN_ERR_HIP : FRNN_OK);
+}
 
 __device__ __forceinline__ unsigned int ld(const unsigned int *p) { return *p; }
 
@@ -127,15 +135,6 @@ __device__ void cc_union(unsigned int *parent, unsigned int u, unsigned int v, C
     }
 }
 
-__device__ __forceinline__ unsigned int wave_min(unsigned int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned int w = static_cast<unsigned int>(__shfl_xor(static_cast<int>(v), o));
-        v = w < v ? w : v;
-    }
-    return v;
-}
-
 __global__ __launch_bounds__(kCcBlock) void k_cc_init(unsigned int *parent, long long n, CcState *state) {
     const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
     for (long long v = static_cast<long long>(blockIdx.x) * kCcBlock + threadIdx.x; v < n; v += stride)
@@ -146,73 +145,116 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_init(unsigned int *parent, long
     }
 }
 
-// Groups of lanes sharing a source root handled as stars per wave pass.
-constexpr int kStarGroups = 4;
+// Hooks each edge's larger endpoint under its smallest neighbour first, so that a
+// cluster whose vertices all neighbour its smallest vertex (the FRNN graph of a
+// track: its points lie within r of one another) is a star before the union-find
+// pass, which then finds equal roots for its edges and swaps nothing.  Lanes of a
+// wave that share a source take the minimum of their targets below it by a
+// segmented reduction (edges come grouped by source), and one lane per source does
+// a device-scope atomicMin on the source's parent.  The parent array then still
+// points only to smaller ids and every entry to a neighbour or itself: each
+// vertex is hooked at most under one neighbour, a valid union of two trees, as
+// every vertex is still a root before this pass.  Whatever this pass leaves
+// unjoined, the union-find pass joins.
+// Edges (or vertices) per lane in the hook and label passes: their loads are all
+// issued before any is used, so a wave keeps several round trips in flight.
+constexpr int kPerLane = 4;
+
+__global__ __launch_bounds__(kCcBlock) void k_cc_minhook(const long long *__restrict__ src,
+                                                         const long long *__restrict__ dst, long long n_edges,
+                                                         long long n, const float *__restrict__ scores,
+                                                         float threshold, unsigned int *parent) {
+    const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
+    const int lane = static_cast<int>(threadIdx.x & 63u);
+    // Wave-aligned bases, so that every lane of a wave takes the same trip count.
+    for (long long e0 = static_cast<long long>(blockIdx.x) * kCcBlock + (threadIdx.x & ~63u); e0 < n_edges;
+         e0 += stride) {
+        const long long e = e0 + lane;
+        unsigned int a = 0xffffffffu, m = 0xffffffffu;
+        if (e < n_edges && !(scores && !(scores[e] > threshold))) {
+            const long long x = src[e], y = dst[e];
+            if (x >= 0 && x < n && y >= 0 && y < n) {  // out-of-range edges are reported by the hook pass
+                a = static_cast<unsigned int>(x);
+                m = static_cast<unsigned int>(y);
+            }
+        }
+        // Minimum over the lanes at or after this one with the same source.
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned int a2 = static_cast<unsigned int>(__shfl_down(static_cast<int>(a), o));
+            const unsigned int m2 = static_cast<unsigned int>(__shfl_down(static_cast<int>(m), o));
+            if (lane + o < 64 && a2 == a && m2 < m) m = m2;
+        }
+        const unsigned int a_prev = static_cast<unsigned int>(__shfl_up(static_cast<int>(a), 1));
+        const bool head = lane == 0 || a_prev != a;
+        if (head && a != 0xffffffffu && m < a) atomicMin(parent + a, m);
+    }
+}
 
 __global__ __launch_bounds__(kCcBlock) void k_cc_hook(const long long *__restrict__ src,
                                                       const long long *__restrict__ dst, long long n_edges,
                                                       long long n, const float *__restrict__ scores,
                                                       float threshold, unsigned int *parent, CcState *state) {
-    const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
-    const int lane = static_cast<int>(threadIdx.x & 63u);
-    // The loop runs over wave-aligned bases so that every lane of a wave takes
-    // the same trip count (the star grouping uses whole-wave ballots).
-    for (long long e0 = static_cast<long long>(blockIdx.x) * kCcBlock + (threadIdx.x & ~63u); e0 < n_edges;
-         e0 += stride) {
-        const long long e = e0 + lane;
-        bool act = e < n_edges && !(scores && !(scores[e] > threshold));
-        unsigned int ra = 0u, rb = 0u;
-        if (act) {
-            const long long a = src[e], b = dst[e];
-            if (a < 0 || a >= n || b < 0 || b >= n) {
+    const long long span = static_cast<long long>(kCcBlock) * kPerLane;
+    const long long stride = static_cast<long long>(gridDim.x) * span;
+    for (long long e0 = static_cast<long long>(blockIdx.x) * span + threadIdx.x; e0 < n_edges; e0 += stride) {
+        unsigned int ra[kPerLane], rb[kPerLane];
+        bool act[kPerLane];
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            const long long e = e0 + static_cast<long long>(kCcBlock) * j;
+            act[j] = e < n_edges && !(scores && !(scores[e] > threshold));
+            const long long a = act[j] ? src[e] : 0, b = act[j] ? dst[e] : 0;
+            if (act[j] && (a < 0 || a >= n || b < 0 || b >= n)) {
                 atomicOr(&state->status, 1u);
-                act = false;
-            } else {
-                ra = static_cast<unsigned int>(a);
-                rb = static_cast<unsigned int>(b);
-                cc_find2(parent, ra, rb);
-                act = ra != rb;
+                act[j] = false;
             }
+            ra[j] = static_cast<unsigned int>(a);
+            rb[j] = static_cast<unsigned int>(b);
         }
-        // Star groups: lanes whose source roots agree join every endpoint root of
-        // the group, and the source root, to the smallest of them.
-        unsigned int hub = ra < rb ? ra : rb;
-        bool leader = false, grouped = false;
-        unsigned long long pend = __builtin_amdgcn_ballot_w64(act);
-        for (int g = 0; g < kStarGroups && pend != 0ull; ++g) {
-            const int lead = __builtin_ctzll(pend);
-            const unsigned int r0 = __builtin_amdgcn_readlane(ra, lead);
-            const unsigned long long grp = __builtin_amdgcn_ballot_w64(ra == r0) & pend;
-            const bool mine = (grp >> lane) & 1ull;
-            unsigned int m = wave_min(mine ? rb : 0xffffffffu);
-            m = m < r0 ? m : r0;
-            if (mine) {
-                hub = m;
-                grouped = true;
-                leader = lane == lead;
-            }
-            pend &= ~grp;
+        // Endpoints with the same parent are in one tree already (the common case
+        // after the min-neighbour pass): no walk to the roots.
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            ra[j] = act[j] ? ld(parent + ra[j]) : 0u;
+            rb[j] = act[j] ? ld(parent + rb[j]) : 0u;
         }
-        if (act) {
-            if (grouped) {
-                cc_union(parent, rb, hub, state);
-                if (leader) cc_union(parent, ra, hub, state);
-            } else {
-                cc_union(parent, ra, rb, state);
-            }
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            if (!act[j] || ra[j] == rb[j]) continue;
+            cc_find2(parent, ra[j], rb[j]);
+            if (ra[j] != rb[j]) cc_union(parent, ra[j], rb[j], state);
         }
     }
 }
 
+// Labels every vertex with its root and counts the roots; the last workgroup to
+// finish writes the caller's result [n_components, status].
 __global__ __launch_bounds__(kCcBlock) void k_cc_label(unsigned int *parent, long long n, long long *labels,
-                                                       CcState *state) {
+                                                       CcState *state, long long *result) {
     __shared__ unsigned long long part[kCcBlock / 64];
-    const long long stride = static_cast<long long>(gridDim.x) * kCcBlock;
+    const long long span = static_cast<long long>(kCcBlock) * kPerLane;
+    const long long stride = static_cast<long long>(gridDim.x) * span;
     unsigned long long roots = 0;
-    for (long long v = static_cast<long long>(blockIdx.x) * kCcBlock + threadIdx.x; v < n; v += stride) {
-        const unsigned int r = cc_find(parent, static_cast<unsigned int>(v));
-        labels[v] = static_cast<long long>(r);
-        roots += r == static_cast<unsigned int>(v) ? 1ull : 0ull;
+    for (long long v0 = static_cast<long long>(blockIdx.x) * span + threadIdx.x; v0 < n; v0 += stride) {
+        // Parents and grandparents of kPerLane vertices requested together; most
+        // trees are one or two levels deep by now.
+        unsigned int p[kPerLane], g[kPerLane];
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            const long long v = v0 + static_cast<long long>(kCcBlock) * j;
+            p[j] = v < n ? ld(parent + v) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) g[j] = ld(parent + p[j]);
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            const long long v = v0 + static_cast<long long>(kCcBlock) * j;
+            if (v >= n) continue;
+            const unsigned int r = g[j] == p[j] ? p[j] : cc_find(parent, g[j]);
+            labels[v] = static_cast<long long>(r);
+            roots += r == static_cast<unsigned int>(v) ? 1ull : 0ull;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) roots += __shfl_xor(roots, o);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = roots;
@@ -220,15 +262,18 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_label(unsigned int *parent, lon
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int w = 0; w < kCcBlock / 64; ++w) t += part[w];
-        if (t) atomicAdd(&state->n_components, t);
+        const unsigned long long old = atomicAdd(&state->done_roots, (1ull << kRootBits) | t);
+        if ((old >> kRootBits) == gridDim.x - 1u) {
+            result[0] = static_cast<long long>((old & kRootMask) + t);
+            result[1] = status_code(state->status);
+        }
     }
 }
 
-// Copies the state into the caller's device result [n_components, status].
+// The caller's device result [n_components, status] of a graph without vertices.
 __global__ void k_cc_result(const CcState *state, long long *result) {
-    const unsigned int s = state->status;
-    result[0] = static_cast<long long>(state->n_components);
-    result[1] = (s & 1u) ? FRNN_ERR_ARG : ((s & 2u) ? FRNN_ERR_HIP : FRNN_OK);
+    result[0] = 0;
+    result[1] = status_code(state->status);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -256,13 +301,18 @@ int enqueue(const int64_t *src, const int64_t *dst, int64_t n_edges, int64_t n_v
     const long long n = n_vertices;
     hipLaunchKernelGGL(k_cc_init, dim3(grid_for(n)), dim3(kCcBlock), 0, s, parent, n, state);
     if (n_edges > 0)
-        hipLaunchKernelGGL(k_cc_hook, dim3(grid_for(n_edges)), dim3(kCcBlock), 0, s,
+        hipLaunchKernelGGL(k_cc_minhook, dim3(grid_for(n_edges)), dim3(kCcBlock), 0, s,
+                           reinterpret_cast<const long long *>(src), reinterpret_cast<const long long *>(dst),
+                           static_cast<long long>(n_edges), n, scores, threshold, parent);
+    if (n_edges > 0)
+        hipLaunchKernelGGL(k_cc_hook, dim3(grid_for((n_edges + kPerLane - 1) / kPerLane)), dim3(kCcBlock), 0, s,
                            reinterpret_cast<const long long *>(src), reinterpret_cast<const long long *>(dst),
                            static_cast<long long>(n_edges), n, scores, threshold, parent, state);
     if (n > 0)
-        hipLaunchKernelGGL(k_cc_label, dim3(grid_for(n)), dim3(kCcBlock), 0, s, parent, n,
-                           reinterpret_cast<long long *>(labels), state);
-    hipLaunchKernelGGL(k_cc_result, dim3(1), dim3(1), 0, s, state, reinterpret_cast<long long *>(result_device));
+        hipLaunchKernelGGL(k_cc_label, dim3(grid_for((n + kPerLane - 1) / kPerLane)), dim3(kCcBlock), 0, s, parent, n,
+                           reinterpret_cast<long long *>(labels), state, reinterpret_cast<long long *>(result_device));
+    else
+        hipLaunchKernelGGL(k_cc_result, dim3(1), dim3(1), 0, s, state, reinterpret_cast<long long *>(result_device));
     return hipGetLastError() == hipSuccess ? FRNN_OK : FRNN_ERR_HIP;
 }
 
