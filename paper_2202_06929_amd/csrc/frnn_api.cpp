@@ -193,6 +193,7 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.sorted_id = cv.take<unsigned int>(2 * rows);
     ws.kept = cv.take<unsigned int>(rows);
     ws.tpos = cv.take<unsigned long long>(rows);
+    ws.inv = cv.take<unsigned int>(rows);
     ws.heavy = cv.take<HeavyEntry>(rows);
     ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap + static_cast<size_t>(edge_capacity));
     ws.tested = cv.take<unsigned long long>(2 * kMaxSearchBlocks);

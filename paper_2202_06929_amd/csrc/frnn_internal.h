@@ -32,6 +32,9 @@ constexpr int kKeptGroup = 64;       // kept tiles per second-level total
 constexpr int kFlatTiles = 4096;     // up to this many kept tiles, placement sums the tile totals directly
 constexpr int kOwnerWindow = 4096;   // output positions mapped to their query at a time in placement
 constexpr int kMaxEvents = 65535;  // events per call (the second grid dimension)
+// A kept count with this bit set belongs to a list of the long-list kernel, whose
+// place is in tpos; other lists sit at kListCap slots per sorted row.
+constexpr unsigned int kKeptLong = 1u << 31;
 
 // One event of a call: its rows in the concatenated points and its share of the
 // cell-key space.  The first event starts at row 0 and cell 0.
@@ -117,8 +120,9 @@ struct Workspace {
     unsigned long long *sums_kept2;  // [groups of kKeptGroup tiles] per-group kept totals
     float *sorted;              // [rows, dpad] points in cell order, zero-padded rows
     unsigned int *sorted_id;    // [2 rows] per sorted row: its original row, then its packed cell
-    unsigned int *kept;         // [rows] neighbours kept per original row
-    unsigned long long *tpos;   // [rows] where each query's list sits in `temp`
+    unsigned int *kept;         // [rows] neighbours kept per original row (| kKeptLong for a long list)
+    unsigned long long *tpos;   // [rows] where a long list sits in `temp` (long lists only)
+    unsigned int *inv;          // [rows] sorted row of each original row
     HeavyEntry *heavy;          // [rows]
     unsigned int *temp;         // [rows * kListCap + edge_capacity] neighbour lists
     unsigned long long *tested; // [2 kMaxSearchBlocks] pairs examined, then pairs fully tested, per search workgroup

@@ -517,7 +517,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
                                                     const unsigned int *__restrict__ cell_start,
                                                     const Counters *__restrict__ ctr,
                                                     float *__restrict__ sorted,
-                                                    unsigned int *__restrict__ sorted_id) {
+                                                    unsigned int *__restrict__ sorted_id,
+                                                    unsigned int *__restrict__ inv) {
     if (ctr->abort) return;
     const EventDesc E = ev[blockIdx.y];
     const Plan P = plans[blockIdx.y];
@@ -551,6 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
         // The original row and the packed cell of a sorted row sit side by side, so
         // the scattered write is one 8-byte store instead of two 4-byte ones.
         reinterpret_cast<uint2 *>(sorted_id)[slot] = make_uint2(static_cast<unsigned int>(gi), pc);
+        inv[gi] = slot;
     }
 }
 
@@ -639,7 +641,6 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                                    const unsigned int *__restrict__ cell_start,
                                                    const Plan *__restrict__ plans, float r2, int K,
                                                    unsigned int *__restrict__ kept,
-                                                   unsigned long long *__restrict__ tpos,
                                                    unsigned int *__restrict__ temp,
                                                    HeavyEntry *__restrict__ heavy,
                                                    Counters *__restrict__ ctr,
@@ -915,11 +916,11 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 if (lane < Qn) {
                     const unsigned int slot = q0 + lane;
                     const unsigned int i = iq;
-                    kept[i] = min(cnt, static_cast<unsigned int>(K));
+                    // One scattered 4-byte store per query: a list that fits sits at its
+                    // sorted row's fixed place, which placement finds through inv.
+                    kept[i] = min(cnt, static_cast<unsigned int>(K)) | (fits ? 0u : kKeptLong);
                     if (cnt > static_cast<unsigned int>(K)) ++capped;
-                    if (fits) {
-                        tpos[i] = static_cast<unsigned long long>(slot) * kListCap;
-                    } else {
+                    if (!fits) {
                         const unsigned int h = atomicAdd(&ctr->heavy_count, 1u);
                         HeavyEntry he;
                         he.slot = slot;
@@ -1065,7 +1066,7 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
 #pragma unroll
             for (int k = 0; k < kPlaceTile / 64; ++k) {
                 const long long idx = b + k * 64 + lane_id();
-                if (idx < n) s += kept[idx];
+                if (idx < n) s += kept[idx] & ~kKeptLong;
             }
             s = wave_sum(s);
             if (lane_id() == 0) {
@@ -1207,6 +1208,7 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                                                        const unsigned long long *__restrict__ sums_kept2,
                                                        int groups_kept, int tiles_kept,
                                                        const unsigned long long *__restrict__ tpos,
+                                                       const unsigned int *__restrict__ inv,
                                                        const unsigned int *__restrict__ temp,
                                                        unsigned long long temp_len, unsigned long long heavy_cap,
                                                        long long *__restrict__ src, long long *__restrict__ dst,
@@ -1280,7 +1282,8 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     const long long i0 = static_cast<long long>(b) * kPlaceTile;
     const int cnt = static_cast<int>(rows - i0 < kPlaceTile ? rows - i0 : kPlaceTile);
     const int q = threadIdx.x;
-    const unsigned int kq = (!abort && q < cnt) ? kept[i0 + q] : 0u;
+    const unsigned int kraw = (!abort && q < cnt) ? kept[i0 + q] : 0u;
+    const unsigned int kq = kraw & ~kKeptLong;
     const unsigned int oq = static_cast<unsigned int>(block_exclusive_scan(kq, scratch));
     if (q < cnt) o[q] = oq;
     if (q == cnt - 1) o[cnt] = oq + kq;
@@ -1302,8 +1305,12 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
         }
     }
     if (abort || overflow) return;
+    // Where the query's list sits in temp: its sorted row's fixed place, or for a
+    // long list the place the long-list kernel chose.
+    unsigned long long tq = 0;
     if (q < cnt) {
-        tp[q] = tpos[i0 + q];
+        tq = (kraw & kKeptLong) ? tpos[i0 + q] : static_cast<unsigned long long>(inv[i0 + q]) * kListCap;
+        tp[q] = tq;
         base_row[q] = n_events == 1 ? 0u : static_cast<unsigned int>(ev[find_event(ev, n_events, i0 + q)].row0);
     }
     const unsigned int total = o[cnt];
@@ -1314,7 +1321,7 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     // found: the query's thread sorts its list (a bitonic network over 16 slots, the
     // unused ones holding the largest value) and stages it in LDS.
     if (q < cnt && kq > 0u) {
-        const unsigned long long t0 = tpos[i0 + q];
+        const unsigned long long t0 = tq;
         if (t0 < fixed_end && t0 + kListCap <= temp_len) {
             const uint4 *l4 = reinterpret_cast<const uint4 *>(temp + t0);
             unsigned int v[kListCap];
@@ -1390,19 +1397,19 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     const long long nb = (static_cast<long long>(a.max_n) + kBlock - 1) / kBlock;
     const int gs = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
     hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, ws.plans,
-                       ws.pcell, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id);
+                       ws.pcell, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id, ws.inv);
     mark(4);
     const unsigned int sq_base = static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves));
     const unsigned int sq_rem = static_cast<unsigned int>(rows % (static_cast<long long>(a.search_blocks) * kWaves));
     if (a.K < kListCap)
         hipLaunchKernelGGL((k_search<DP, true>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
                            ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
-                           a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
+                           a.r2, a.K, ws.kept, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
                            a.search_prio);
     else
         hipLaunchKernelGGL((k_search<DP, false>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
                            ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
-                           a.r2, a.K, ws.kept, ws.tpos, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
+                           a.r2, a.K, ws.kept, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
                            a.search_prio);
     mark(5);
     const unsigned long long heavy_base = static_cast<unsigned long long>(rows) * kListCap;
@@ -1477,7 +1484,7 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
     mark(6);
     hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
                        ws.rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n,
-                       ws.tiles_kept_n, ws.tpos,
+                       ws.tiles_kept_n, ws.tpos, ws.inv,
                        ws.temp, static_cast<unsigned long long>(ws.rows) * kListCap + a.edge_capacity,
                        a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, ws.tested, ws.capped_blk,
                        a.search_blocks, a.edge_off_out ? a.edge_off_out : ws.edge_off,
