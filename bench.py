@@ -3,8 +3,8 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|high|tiny]
 
 A step is one pass of the whole path over one synthetic event already resident in
-HBM: bounds, keys, cell scan, scatter, neighbour search, long lists and edge
-placement.  The timed steps run back to back on one stream through the
+HBM: bounds, keys, cell scan, scatter, neighbour search and edge placement (long
+lists included).  The timed steps run back to back on one stream through the
 asynchronous entry point; synchronous calls (each returning the edge count to the
 host) give the per-event latency percentiles.  The default workload is
 the single event of 120,000 points in 8-D (r = 0.1, K = 256).
@@ -72,9 +72,10 @@ def parse():
 
 
 def search_bytes(n: int, dpad: int, n_cells: int, E: int) -> int:
-    """Algorithmic HBM bytes of one search launch: each sorted row read once,
-    row ids, cell starts, kept counts and list positions, the unsorted edge store."""
-    return n * dpad * 4 + 4 * n + 4 * (n_cells + 1) + 4 * n + 8 * n + 4 * E
+    """Algorithmic HBM bytes of one search launch: each sorted row read once, the
+    sorted rows' (original row, cell) words, cell starts, kept counts and the
+    unsorted neighbour lists (4 bytes per edge)."""
+    return n * dpad * 4 + 8 * n + 4 * (n_cells + 1) + 4 * n + 4 * E
 
 
 def path_bytes(n: int, d: int, E: int) -> int:

@@ -94,8 +94,9 @@ enum frnn_stage {
     FRNN_STAGE_CELLS = 2,    /* scan of the histogram */
     FRNN_STAGE_SCATTER = 3,  /* rows copied into cell order */
     FRNN_STAGE_SEARCH = 4,   /* neighbour-cell search */
-    FRNN_STAGE_LONG = 5,     /* kept totals, long neighbour lists and the K cap */
-    FRNN_STAGE_PLACE = 6,    /* output offsets; edges written in (i, j) order */
+    FRNN_STAGE_TOTALS = 5,   /* kept neighbours per tile of 256 queries */
+    FRNN_STAGE_PLACE = 6,    /* output offsets, long neighbour lists and the K cap; edges
+                                written in (i, j) order */
     FRNN_STAGES = 7
 };
 
@@ -109,15 +110,17 @@ typedef struct frnn_stats {
     int32_t dims[4];            /* binned coordinates (-1 past `axes`) */
     float cell[4];              /* cell edge per binned axis (infinite past `axes`) */
     int32_t capped_queries;     /* queries with |N(i)| > K */
-    int32_t overflow_queries;   /* queries handled by the long-list path */
+    int32_t overflow_queries;   /* queries whose list the placement pass collects again (more
+                                   than 16 neighbours, or more than K when K >= 16) */
     float stage_ms[FRNN_STAGES]; /* per-stage device time with FRNN_FLAG_TIMING, else 0 */
     int64_t survivors;          /* examined pairs whose leading partial sum stayed below r2, so
                                    that the search added the remaining terms of the distance */
 } frnn_stats;
 
-/* Bytes of device workspace frnn_build needs for n points of dimension d and
- * room for edge_capacity edges.  Host-only arithmetic; returns 0 for invalid
- * arguments (n < 0, d outside [3, 64], edge_capacity < 0). */
+/* Bytes of device workspace frnn_build needs for n points of dimension d (the
+ * size does not depend on edge_capacity, which is only checked).  Host-only
+ * arithmetic; returns 0 for invalid arguments (n < 0, d outside [3, 64],
+ * edge_capacity < 0). */
 size_t frnn_workspace_bytes(int64_t n, int32_t d, int64_t edge_capacity);
 
 /* Builds the FRNN graph of the points.
@@ -164,7 +167,7 @@ int frnn_build_noalloc(const float *points, int64_t n, int32_t d, float r, int32
                        const frnn_config *config, frnn_stats *stats, void *stream);
 
 /* Bytes of device workspace frnn_build_batch needs for the given events (see
- * below) and room for edge_capacity edges in total.  Returns 0 for invalid
+ * below); edge_capacity is only checked.  Returns 0 for invalid
  * arguments. */
 size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events, int32_t d,
                                   int64_t edge_capacity);

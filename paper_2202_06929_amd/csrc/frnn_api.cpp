@@ -168,7 +168,7 @@ long long describe_events(const int64_t *event_offsets, int n_events, EventDesc 
     return cells;
 }
 
-Workspace layout(void *base, long long rows, long long cells, int n_events, int d, int64_t edge_capacity) {
+Workspace layout(void *base, long long rows, long long cells, int n_events, int d) {
     const int dpad = dpad_for(d);
     const int64_t tiles_cells = (cells + 1 + kScanTile - 1) / kScanTile;
     const int64_t tiles_kept = rows > 0 ? (rows + kPlaceTile - 1) / kPlaceTile : 1;
@@ -192,10 +192,8 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.sorted = cv.take<float>(static_cast<size_t>(rows + 1) * dpad);
     ws.sorted_id = cv.take<unsigned int>(2 * rows);
     ws.kept = cv.take<unsigned int>(rows);
-    ws.tpos = cv.take<unsigned long long>(rows);
     ws.inv = cv.take<unsigned int>(rows);
-    ws.heavy = cv.take<HeavyEntry>(rows);
-    ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap + static_cast<size_t>(edge_capacity));
+    ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap);
     ws.tested = cv.take<unsigned long long>(2 * kMaxSearchBlocks);
     ws.capped_blk = cv.take<unsigned int>(kMaxSearchBlocks);
     ws.rows = rows;
@@ -286,7 +284,7 @@ int enqueue(const EventDesc *descs, int n_events, long long rows, long long cell
     a.ev_from_arg = n_events == 1 ? 1 : 0;
     a.edge_off_out = edge_off_out;
     a.report_out = report_out;
-    const Workspace ws = layout(workspace, rows, cells, n_events, d, edge_capacity);
+    const Workspace ws = layout(workspace, rows, cells, n_events, d);
     const bool timing = config && (config->flags & FRNN_FLAG_TIMING);
     a.events = nullptr;
     if (timing) {
@@ -385,7 +383,7 @@ void init_stats(frnn_stats *stats, const frnn_config *config, int d) {
 extern "C" size_t frnn_workspace_bytes(int64_t n, int32_t d, int64_t edge_capacity) {
     if (n < 0 || n >= (int64_t{1} << 31) || d < 3 || d > FRNN_MAX_D || edge_capacity < 0) return 0;
     const int64_t offs[2] = {0, n};
-    return layout(nullptr, n, describe_events(offs, 1, nullptr), 1, d, edge_capacity).total_bytes;
+    return layout(nullptr, n, describe_events(offs, 1, nullptr), 1, d).total_bytes;
 }
 
 extern "C" size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events, int32_t d,
@@ -394,7 +392,7 @@ extern "C" size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32
     int max_n = 0;
     if (d < 3 || d > FRNN_MAX_D || edge_capacity < 0) return 0;
     if (check_events(event_offsets, n_events, &rows, &max_n, &cells) != FRNN_OK) return 0;
-    return layout(nullptr, rows, cells, n_events, d, edge_capacity).total_bytes;
+    return layout(nullptr, rows, cells, n_events, d).total_bytes;
 }
 
 extern "C" const char *frnn_status_string(int status) {
@@ -451,7 +449,7 @@ extern "C" int frnn_build_batch(const float *points, const int64_t *event_offset
     if (rows == 0) return FRNN_OK;
     if (!points || !workspace || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
-    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d, edge_capacity).total_bytes)
+    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d).total_bytes)
         return FRNN_ERR_WORKSPACE;
     std::vector<EventDesc> descs(n_events);
     describe_events(event_offsets, n_events, descs.data());
@@ -481,7 +479,7 @@ extern "C" int frnn_build_batch_async(const float *points, const int64_t *event_
     if (rows == 0) return FRNN_ERR_ARG;
     if (!points || !workspace || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
-    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d, edge_capacity).total_bytes)
+    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d).total_bytes)
         return FRNN_ERR_WORKSPACE;
     std::vector<EventDesc> descs(n_events);
     describe_events(event_offsets, n_events, descs.data());
@@ -515,7 +513,7 @@ extern "C" int frnn_build_events_async(const float *const *event_points, const i
     if (rows == 0) return FRNN_ERR_ARG;
     if (!workspace || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
-    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d, edge_capacity).total_bytes)
+    if (workspace_bytes < layout(nullptr, rows, cells, n_events, d).total_bytes)
         return FRNN_ERR_WORKSPACE;
     std::vector<EventDesc> descs(n_events);
     describe_events(offs.data(), n_events, descs.data());

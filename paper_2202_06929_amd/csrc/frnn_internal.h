@@ -32,8 +32,9 @@ constexpr int kKeptGroup = 64;       // kept tiles per second-level total
 constexpr int kFlatTiles = 4096;     // up to this many kept tiles, placement sums the tile totals directly
 constexpr int kOwnerWindow = 4096;   // output positions mapped to their query at a time in placement
 constexpr int kMaxEvents = 65535;  // events per call (the second grid dimension)
-// A kept count with this bit set belongs to a list of the long-list kernel, whose
-// place is in tpos; other lists sit at kListCap slots per sorted row.
+// A kept count with this bit set belongs to a long list (more than kListCap
+// neighbours, or more than K without the search's own selection), which the
+// placement pass collects again; other lists sit at kListCap slots per sorted row.
 constexpr unsigned int kKeptLong = 1u << 31;
 
 // One event of a call: its rows in the concatenated points and its share of the
@@ -73,13 +74,14 @@ struct Plan {
 __host__ __device__ constexpr int cell_bits(int axes) { return axes == 4 ? 8 : 10; }
 
 // Single-address atomics serialise across the chip (about 11 ns each), so these
-// are touched only by rare events (long lists, capped queries, bad input).
+// are touched only by rare events (long lists, bad input).
 struct Counters {
-    unsigned long long heavy_top;  // next free slot of the long-list store
-    unsigned int heavy_count;      // queries sent to the long-list path
-    unsigned int capped;           // queries with more than K neighbours
+    unsigned int heavy_count;      // queries whose list is long
     unsigned int abort;            // some event had a non-finite coordinate
+    unsigned int capped;           // queries with more than K neighbours (summed after the search)
     unsigned int pad;
+    unsigned long long tested;     // pairs examined, summed over the search workgroups
+    unsigned long long survived;   // pairs that reached the second stage, likewise
 };
 
 // Result summary copied to the host at the end of a call (event 0's grid).
@@ -93,14 +95,6 @@ struct Report {
     int n_cells;
     int G[kMaxAxes];
     float c[kMaxAxes];
-};
-
-// A query whose neighbour list did not fit the list of the main search.
-struct HeavyEntry {
-    unsigned int slot;    // position of the query in cell order
-    unsigned int count;   // |N(i)| before the cap
-    unsigned int pcell;   // packed coordinates of its cell
-    unsigned int event;   // its event
 };
 
 // Device buffers of one call, carved from the caller's workspace.
@@ -117,14 +111,12 @@ struct Workspace {
     unsigned int *cell_start;   // [cells + 1] exclusive scan of the histogram
     unsigned long long *sums_cells;  // [tiles of cells + 1] per-tile histogram totals
     unsigned long long *sums_kept;   // [tiles of kPlaceTile rows] per-tile kept totals
-    unsigned long long *sums_kept2;  // [groups of kKeptGroup tiles] per-group kept totals
+    unsigned long long *sums_kept2;  // [groups of kKeptGroup tiles] per-group kept totals (more than kFlatTiles tiles)
     float *sorted;              // [rows, dpad] points in cell order, zero-padded rows
     unsigned int *sorted_id;    // [2 rows] per sorted row: its original row, then its packed cell
     unsigned int *kept;         // [rows] neighbours kept per original row (| kKeptLong for a long list)
-    unsigned long long *tpos;   // [rows] where a long list sits in `temp` (long lists only)
     unsigned int *inv;          // [rows] sorted row of each original row
-    HeavyEntry *heavy;          // [rows]
-    unsigned int *temp;         // [rows * kListCap + edge_capacity] neighbour lists
+    unsigned int *temp;         // [rows * kListCap] neighbour lists of up to kListCap entries
     unsigned long long *tested; // [2 kMaxSearchBlocks] pairs examined, then pairs fully tested, per search workgroup
     unsigned int *capped_blk;   // [kMaxSearchBlocks] capped queries per search workgroup
     long long rows;

@@ -9,18 +9,19 @@
 //   k_scan_tiles  exclusive scan of the histogram -> first sorted row of each cell
 //   k_scatter     counting-sort scatter: rows copied into cell order
 //   k_search      each wave takes an equal share of the queries in cell order: a
-//                 cell's queries against the (2R+1)^2 contiguous x-runs of
-//                 neighbouring cells; each lane holds one candidate (its leading
-//                 coordinates, or its whole row for rows wider than 8 floats), query
-//                 rows are wave-uniform; an exact early exit after the first two to
-//                 four terms of the distance sum; ballots queue the survivors, whose
-//                 sums are finished 64 at a time; each list is stored as found
-//   k_heavy       kept totals per tile and per group of tiles; queries whose list
-//                 is longer than the search keeps, or longer than K: the K smallest
-//                 by (D, j) found by an MSB-first radix select
-//   k_place       output offsets from the totals and a block scan; each short list
-//                 sorted by its query's thread and staged in LDS; the edges written
-//                 to their (i asc, j asc) positions with coalesced stores
+//                 cell's queries against the (2R+1)^(axes-1) contiguous runs of
+//                 neighbouring cells along axis 0; each lane holds one candidate (its
+//                 leading coordinates, or its whole row for rows wider than 8
+//                 floats), query rows are wave-uniform; an exact early exit after the
+//                 first two to four terms of the distance sum; ballots queue the
+//                 survivors, whose sums are finished 64 at a time; each list is
+//                 stored as found
+//   k_kept_sums   kept totals per placement tile and per group of tiles
+//   k_place       output offsets from the totals and a block scan; lists longer
+//                 than the search keeps, or longer than K, collected again by the
+//                 block (the K smallest by (D, j) from an MSB-first radix select);
+//                 each short list sorted by its query's thread and staged in LDS; the
+//                 edges written to their (i asc, j asc) positions with coalesced stores
 //
 // Distances follow one fixed order with every product and sum rounded on its
 // own: this file is compiled with -ffp-contract=off and the pragma below.
@@ -642,7 +643,6 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                                    const Plan *__restrict__ plans, float r2, int K,
                                                    unsigned int *__restrict__ kept,
                                                    unsigned int *__restrict__ temp,
-                                                   HeavyEntry *__restrict__ heavy,
                                                    Counters *__restrict__ ctr,
                                                    unsigned long long *__restrict__ tested_out,
                                                    unsigned int *__restrict__ capped_out, int prio) {
@@ -706,7 +706,6 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     // (q_base and q_rem come from the host, so no division runs here).
     const unsigned int q_lo = gw * q_base + min(gw, q_rem);
     const unsigned int q_hi = q_lo + q_base + (gw < q_rem ? 1u : 0u);
-    int ev_cur = -1;
     Plan P;
     RunLane rl;
     unsigned int cell0 = 0;
@@ -724,7 +723,6 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
             const unsigned int qs = win + t0;
             if (qs >= ev_end) {
                 const int e = n_events == 1 ? 0 : find_event(ev, n_events, qs);
-                ev_cur = e;
                 P = plans[e];
                 const EventDesc E = ev[e];
                 cell0 = static_cast<unsigned int>(E.cell0);
@@ -910,25 +908,18 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     __shfl(static_cast<int>(v_orig), static_cast<int>((q0 - win + lane) & 63u)));
                 wave_lds_sync();
                 // Kept counts for every query; lists that fit are stored at a fixed place
-                // (kListCap slots per sorted row), longer ones go to the long-list kernel.
+                // (kListCap slots per sorted row), longer ones are collected again by the
+                // placement pass.
                 const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
                                   (SEL || cnt <= static_cast<unsigned int>(K));
                 if (lane < Qn) {
-                    const unsigned int slot = q0 + lane;
                     const unsigned int i = iq;
                     // One scattered 4-byte store per query: a list that fits sits at its
                     // sorted row's fixed place, which placement finds through inv.
-                    kept[i] = min(cnt, static_cast<unsigned int>(K)) | (fits ? 0u : kKeptLong);
+                    const unsigned int kq = min(cnt, static_cast<unsigned int>(K));
+                    kept[i] = kq | (fits ? 0u : kKeptLong);
                     if (cnt > static_cast<unsigned int>(K)) ++capped;
-                    if (!fits) {
-                        const unsigned int h = atomicAdd(&ctr->heavy_count, 1u);
-                        HeavyEntry he;
-                        he.slot = slot;
-                        he.count = cnt;
-                        he.pcell = pc;
-                        he.event = static_cast<unsigned int>(ev_cur);
-                        heavy[h] = he;
-                    }
+                    if (!fits) atomicAdd(&ctr->heavy_count, 1u);
                 }
                 // Lists that fit go to their fixed place (kListCap slots per sorted row)
                 // as found, in 16-byte pieces; the placement pass orders every such list
@@ -1027,166 +1018,175 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     }
 }
 
+// --------------------------------------------------------------- kept totals
+
+// Totals of the kept counts per placement tile, one wave per tile, and per group
+// of kKeptGroup tiles (spread-address atomics into totals cleared by the bounds
+// pass).  Block 0 also sums the search's per-workgroup counts for the report,
+// off the placement pass's critical path.
+__global__ __launch_bounds__(kBlock) void k_kept_sums(int n, const unsigned int *__restrict__ kept,
+                                                      unsigned long long *__restrict__ sums_kept,
+                                                      unsigned long long *__restrict__ sums_kept2, int tiles_kept,
+                                                      const unsigned long long *__restrict__ tested,
+                                                      const unsigned int *__restrict__ capped_blk,
+                                                      int search_blocks, Counters *__restrict__ ctr) {
+    if (ctr->abort) return;
+    if (blockIdx.x == 0) {
+        __shared__ unsigned long long red[kWaves];
+        unsigned long long t = 0, sv = 0, cp = 0;
+        for (int k = threadIdx.x; k < search_blocks; k += kBlock) {
+            t += tested[k];
+            sv += tested[kMaxSearchBlocks + k];
+            cp += capped_blk[k];
+        }
+        t = block_sum(t, red);
+        sv = block_sum(sv, red);
+        cp = block_sum(cp, red);
+        if (threadIdx.x == 0) {
+            ctr->tested = t;
+            ctr->survived = sv;
+            ctr->capped = static_cast<unsigned int>(cp);
+        }
+    }
+    const int nw = static_cast<int>(gridDim.x) * kWaves;
+    for (int t = static_cast<int>(blockIdx.x) * kWaves + wave_id(); t < tiles_kept; t += nw) {
+        const long long b = static_cast<long long>(t) * kPlaceTile;
+        unsigned long long s = 0;
+#pragma unroll
+        for (int k = 0; k < kPlaceTile / 64; ++k) {
+            const long long idx = b + k * 64 + lane_id();
+            if (idx < n) s += kept[idx] & ~kKeptLong;
+        }
+        s = wave_sum(s);
+        if (lane_id() == 0) {
+            sums_kept[t] = s;
+            if (s && tiles_kept > kFlatTiles) atomicAdd(&sums_kept2[t / kKeptGroup], s);
+        }
+    }
+}
+
 // --------------------------------------------------------------- long lists
 
-constexpr int kHeavyBlocks = 256;
-
+// LDS of the long-list collection (besides the kept ids, which go to the
+// placement pass's staging array: it holds nothing yet at that point).
 template <int DP>
-__global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sorted,
-                                                  const unsigned int *__restrict__ sorted_id,
-                                                  const unsigned int *__restrict__ cell_start,
-                                                  const EventDesc *__restrict__ ev,
-                                                  const Plan *__restrict__ plans, float r2, int K, int n,
-                                                  const unsigned int *__restrict__ kept,
-                                                  unsigned long long *__restrict__ sums_kept,
-                                                  unsigned long long *__restrict__ sums_kept2, int tiles_kept,
-                                                  unsigned long long *__restrict__ tpos,
-                                                  unsigned int *__restrict__ temp,
-                                                  unsigned long long heavy_base, unsigned long long heavy_cap,
-                                                  const HeavyEntry *__restrict__ heavy,
-                                                  Counters *__restrict__ ctr) {
-    __shared__ unsigned int buf[kMaxK];
-    __shared__ unsigned int hist[256];
-    __shared__ __align__(16) float qv[DP];
-    __shared__ unsigned int run_start[64];
-    __shared__ unsigned int run_pre[65];
-    __shared__ unsigned int fill_s;
-    __shared__ unsigned long long prefix_s, base_s;
-    __shared__ unsigned int remaining_s;
+struct LongLds {
+    unsigned int hist[256];
+    __align__(16) float qv[DP];
+    unsigned int run_start[64];
+    unsigned int run_pre[65];
+    unsigned int fill;
+    unsigned int remaining;
+    unsigned long long prefix;
+};
 
-    if (ctr->abort) return;
-
-    // Totals of kept counts (final for every query) per placement tile, one wave
-    // per tile, and per group of kKeptGroup tiles (spread-address atomics).
-    {
-        const int nw = static_cast<int>(gridDim.x) * kWaves;
-        for (int t = static_cast<int>(blockIdx.x) * kWaves + wave_id(); t < tiles_kept; t += nw) {
-            const long long b = static_cast<long long>(t) * kPlaceTile;
-            unsigned long long s = 0;
-#pragma unroll
-            for (int k = 0; k < kPlaceTile / 64; ++k) {
-                const long long idx = b + k * 64 + lane_id();
-                if (idx < n) s += kept[idx] & ~kKeptLong;
-            }
-            s = wave_sum(s);
-            if (lane_id() == 0) {
-                sums_kept[t] = s;
-                if (s && tiles_kept > kFlatTiles) atomicAdd(&sums_kept2[t / kKeptGroup], s);
-            }
-        }
+// One long list, collected again by the whole workgroup (every thread calls this
+// with the same arguments): the query's candidates are enumerated over the same
+// runs of cells as in the search; with `select` (its kept count is K, so it may
+// have more than K hits) the K first hits in (D, j) order are found by an
+// MSB-first radix select over (D bits << 32 | j) keys, D being never negative;
+// the kept ids are sorted by a bitonic network in LDS and written, local to the
+// query's event, to out[0, n_out).
+template <int DP>
+__device__ void long_list(const float *__restrict__ sorted, const unsigned int *__restrict__ sorted_id,
+                          const unsigned int *__restrict__ cell_start, const Plan &P, unsigned int cell0,
+                          unsigned int slot, float r2, unsigned int n_out, bool select, long long row0,
+                          long long *__restrict__ out, unsigned int *__restrict__ buf, LongLds<DP> &L) {
+    const int nruns = run_count(P);
+    for (int k = threadIdx.x; k < DP; k += kPlaceBlock) L.qv[k] = sorted[static_cast<size_t>(slot) * DP + k];
+    if (wave_id() == 0) {
+        int u[kMaxAxes];
+        unpack_cell(sorted_id[2u * slot + 1u], P.axes, u);
+        unsigned int start, pre, end;
+        const unsigned int M = wave_runs(u, cell0, P, run_lane(P), cell_start, start, pre, end);
+        L.run_start[lane_id()] = start;
+        L.run_pre[lane_id()] = pre;
+        if (lane_id() == 0) L.run_pre[64] = M;
     }
-
-    const unsigned int n_heavy = ctr->heavy_count;
-    for (unsigned int h = blockIdx.x; h < n_heavy; h += gridDim.x) {
-        const HeavyEntry he = heavy[h];
-        const Plan P = plans[he.event];
-        const unsigned int cell0 = static_cast<unsigned int>(ev[he.event].cell0);
-        const int nruns = run_count(P);
-        for (int k = threadIdx.x; k < DP; k += kBlock) qv[k] = sorted[static_cast<size_t>(he.slot) * DP + k];
-        if (wave_id() == 0) {
-            int u[kMaxAxes];
-            unpack_cell(he.pcell, P.axes, u);
-            unsigned int start, pre, end;
-            const unsigned int M = wave_runs(u, cell0, P, run_lane(P), cell_start, start, pre, end);
-            run_start[lane_id()] = start;
-            run_pre[lane_id()] = pre;
-            if (lane_id() == 0) run_pre[64] = M;
-        }
-        __syncthreads();
-        const unsigned int M = run_pre[64];
-        float q[DP];
+    __syncthreads();
+    const unsigned int M = L.run_pre[64];
+    float q[DP];
 #pragma unroll
-        for (int k = 0; k < DP; ++k) q[k] = qv[k];
+    for (int k = 0; k < DP; ++k) q[k] = L.qv[k];
 
-        // (D bits << 32 | j) orders hits by (D, j): D is never negative.
-        auto hit_key = [&](unsigned int m, bool &ok) -> unsigned long long {
-            int r = 0;
-            for (int t = 1; t < nruns; ++t) r += (m >= run_pre[t]) ? 1 : 0;
-            const unsigned int s = run_start[r] + (m - run_pre[r]);
-            float c[DP];
-            load_row<DP>(sorted, s, c);
-            const float D = sq_dist<DP>(c, q);
-            ok = (D < r2) && (s != he.slot);
-            return (static_cast<unsigned long long>(__float_as_uint(D)) << 32) | sorted_id[2u * s];
-        };
+    auto hit_key = [&](unsigned int m, bool &ok) -> unsigned long long {
+        int r = 0;
+        for (int t = 1; t < nruns; ++t) r += (m >= L.run_pre[t]) ? 1 : 0;
+        const unsigned int s = L.run_start[r] + (m - L.run_pre[r]);
+        float c[DP];
+        load_row<DP>(sorted, s, c);
+        const float D = sq_dist<DP>(c, q);
+        ok = (D < r2) && (s != slot);
+        return (static_cast<unsigned long long>(__float_as_uint(D)) << 32) | sorted_id[2u * s];
+    };
 
-        unsigned int n_out;
-        unsigned long long limit = ~0ull;  // keep hits with key <= limit
-        if (he.count > static_cast<unsigned int>(K)) {
-            if (threadIdx.x == 0) {
-                prefix_s = 0ull;
-                remaining_s = static_cast<unsigned int>(K);
-            }
-            for (int pass = 0; pass < 8; ++pass) {
-                const int shift = 56 - 8 * pass;
-                for (int b = threadIdx.x; b < 256; b += kBlock) hist[b] = 0u;
-                __syncthreads();
-                const unsigned long long prefix = prefix_s;
-                for (unsigned int m = threadIdx.x; m < M; m += kBlock) {
-                    bool ok;
-                    const unsigned long long key = hit_key(m, ok);
-                    const bool match = pass == 0 || (key >> (shift + 8)) == (prefix >> (shift + 8));
-                    if (ok && match) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
-                }
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    unsigned int rem = remaining_s, b = 0;
-                    while (b < 255 && hist[b] < rem) {
-                        rem -= hist[b];
-                        ++b;
-                    }
-                    remaining_s = rem;
-                    prefix_s = prefix | (static_cast<unsigned long long>(b) << shift);
-                }
-                __syncthreads();
-            }
-            limit = prefix_s;
-            n_out = static_cast<unsigned int>(K);
-        } else {
-            n_out = he.count;
-        }
-        if (threadIdx.x == 0) fill_s = 0u;
-        __syncthreads();
-        for (unsigned int m = threadIdx.x; m < M; m += kBlock) {
-            bool ok;
-            const unsigned long long key = hit_key(m, ok);
-            if (ok && key <= limit) {
-                const unsigned int pos = atomicAdd(&fill_s, 1u);
-                if (pos < static_cast<unsigned int>(kMaxK)) buf[pos] = static_cast<unsigned int>(key & 0xffffffffull);
-            }
-        }
-        __syncthreads();
-        // Bitonic sort of buf[0, n_out) by neighbour id.
-        unsigned int size = 1;
-        while (size < n_out) size <<= 1;
-        for (unsigned int e = n_out + threadIdx.x; e < size; e += kBlock) buf[e] = 0xffffffffu;
-        __syncthreads();
-        for (unsigned int k = 2; k <= size; k <<= 1) {
-            for (unsigned int j = k >> 1; j > 0; j >>= 1) {
-                for (unsigned int e = threadIdx.x; e < size; e += kBlock) {
-                    const unsigned int o = e ^ j;
-                    if (o > e) {
-                        const unsigned int a = buf[e], b = buf[o];
-                        const bool up = (e & k) == 0;
-                        if ((a > b) == up) {
-                            buf[e] = b;
-                            buf[o] = a;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
+    unsigned long long limit = ~0ull;  // keep hits with key <= limit
+    if (select) {
         if (threadIdx.x == 0) {
-            base_s = atomicAdd(&ctr->heavy_top, static_cast<unsigned long long>(n_out));
-            tpos[sorted_id[2u * he.slot]] = heavy_base + base_s;
+            L.prefix = 0ull;
+            L.remaining = n_out;
         }
-        __syncthreads();
-        const unsigned long long base = base_s;
-        if (base + n_out <= heavy_cap)
-            for (unsigned int t = threadIdx.x; t < n_out; t += kBlock) temp[heavy_base + base + t] = buf[t];
-        __syncthreads();
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            for (int b = threadIdx.x; b < 256; b += kPlaceBlock) L.hist[b] = 0u;
+            __syncthreads();
+            const unsigned long long prefix = L.prefix;
+            for (unsigned int m = threadIdx.x; m < M; m += kPlaceBlock) {
+                bool ok;
+                const unsigned long long key = hit_key(m, ok);
+                const bool match = pass == 0 || (key >> (shift + 8)) == (prefix >> (shift + 8));
+                if (ok && match) atomicAdd(&L.hist[(key >> shift) & 255ull], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned int rem = L.remaining, b = 0;
+                while (b < 255 && L.hist[b] < rem) {
+                    rem -= L.hist[b];
+                    ++b;
+                }
+                L.remaining = rem;
+                L.prefix = prefix | (static_cast<unsigned long long>(b) << shift);
+            }
+            __syncthreads();
+        }
+        limit = L.prefix;
     }
+    if (threadIdx.x == 0) L.fill = 0u;
+    __syncthreads();
+    for (unsigned int m = threadIdx.x; m < M; m += kPlaceBlock) {
+        bool ok;
+        const unsigned long long key = hit_key(m, ok);
+        if (ok && key <= limit) {
+            const unsigned int pos = atomicAdd(&L.fill, 1u);
+            if (pos < static_cast<unsigned int>(kMaxK)) buf[pos] = static_cast<unsigned int>(key & 0xffffffffull);
+        }
+    }
+    __syncthreads();
+    // Bitonic sort of buf by neighbour id; slots past the hits found hold the
+    // largest value (only a corrupted kept count could leave any of them in [0, n_out)).
+    const unsigned int found = min(L.fill, static_cast<unsigned int>(kMaxK));
+    unsigned int size = 1;
+    while (size < n_out) size <<= 1;
+    for (unsigned int e = found + threadIdx.x; e < size; e += kPlaceBlock) buf[e] = 0xffffffffu;
+    __syncthreads();
+    for (unsigned int k = 2; k <= size; k <<= 1) {
+        for (unsigned int j = k >> 1; j > 0; j >>= 1) {
+            for (unsigned int e = threadIdx.x; e < size; e += kPlaceBlock) {
+                const unsigned int o = e ^ j;
+                if (o > e) {
+                    const unsigned int a = buf[e], b = buf[o];
+                    const bool up = (e & k) == 0;
+                    if ((a > b) == up) {
+                        buf[e] = b;
+                        buf[o] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (unsigned int t = threadIdx.x; t < n_out; t += kPlaceBlock) out[t] = static_cast<long long>(buf[t]) - row0;
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------- place
@@ -1194,53 +1194,83 @@ __global__ __launch_bounds__(kBlock) void k_heavy(const float *__restrict__ sort
 // Block b owns queries [kPlaceTile b, kPlaceTile (b + 1)), one per thread.  Its
 // first output position is the sum of the kept totals before it (whole groups of
 // kKeptGroup tiles, then the tiles of its own group); a block scan of its kept
-// counts gives each query's offset.  Output positions are then mapped to their
-// query through an owner table in LDS, a window at a time, so that consecutive
-// threads write consecutive int64 positions.  Lists in the fixed kListCap-slot
-// places come from the search in the order their hits were found: each query's
-// thread sorts its list in registers and stages it in LDS first.  Long lists come
-// sorted from the long-list kernel.  Indices are
-// made local to each query's event.  Block 0 writes the report and the status; the
-// block holding an event's first row writes its edge offset.
+// counts gives each query's offset.  Long lists of the block's queries are
+// collected again and written first, one at a time by the whole block.  Output
+// positions are then mapped to their query through an owner table in LDS, a
+// window at a time, so that consecutive threads write consecutive int64
+// positions.  Lists in the fixed kListCap-slot places come from the search in the
+// order their hits were found: each query's thread sorts its list in registers and
+// stages it in LDS first.  Indices are made local to each query's event.  Block 0
+// writes the report and the status; the block holding an event's first row writes
+// its edge offset.
+template <int DP>
 __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const EventDesc *__restrict__ ev,
                                                        int n_events, const unsigned int *__restrict__ kept,
                                                        const unsigned long long *__restrict__ sums_kept,
                                                        const unsigned long long *__restrict__ sums_kept2,
                                                        int groups_kept, int tiles_kept,
-                                                       const unsigned long long *__restrict__ tpos,
                                                        const unsigned int *__restrict__ inv,
                                                        const unsigned int *__restrict__ temp,
-                                                       unsigned long long temp_len, unsigned long long heavy_cap,
+                                                       const float *__restrict__ sorted,
+                                                       const unsigned int *__restrict__ sorted_id,
+                                                       const unsigned int *__restrict__ cell_start, float r2, int K,
                                                        long long *__restrict__ src, long long *__restrict__ dst,
                                                        unsigned long long cap, const Plan *__restrict__ plans,
                                                        const Counters *__restrict__ ctr,
-                                                       const unsigned long long *__restrict__ tested,
-                                                       const unsigned int *__restrict__ capped_blk,
-                                                       int search_blocks, long long *__restrict__ edge_off,
+                                                       long long *__restrict__ edge_off,
                                                        Report *__restrict__ report) {
     static_assert(kPlaceBlock == kPlaceTile && kPlaceTile <= 256, "one query per thread, owner ids fit a byte");
+    static_assert(kPlaceTile * kListCap >= kMaxK, "the staging array holds a long list");
     __shared__ unsigned int o[kPlaceTile + 1];
-    __shared__ unsigned long long tp[kPlaceTile];
     __shared__ unsigned int base_row[kPlaceTile];
     __shared__ unsigned char owner[kOwnerWindow];
+    __shared__ unsigned char kind[kPlaceTile];    // 1: list at the fixed place, 2: long list, 0: none
+    __shared__ unsigned char long_q[kPlaceTile];  // the block's long-list queries, in order
+    __shared__ unsigned int n_long_s;
     __shared__ __align__(16) unsigned int staged[kPlaceTile * kListCap];  // sorted fixed-place lists
     __shared__ unsigned long long scratch[kWaves];
+    __shared__ LongLds<DP> L;
     const bool abort = ctr->abort != 0;
     const int b = static_cast<int>(blockIdx.x);
     const int g = b / kKeptGroup;
+    const long long i0 = static_cast<long long>(b) * kPlaceTile;
+    const int cnt = static_cast<int>(rows - i0 < kPlaceTile ? rows - i0 : kPlaceTile);
+    const int q = threadIdx.x;
+    // The query's kept count, its sorted row (whose fixed place holds a list of up
+    // to kListCap) and that list are requested first, so that their round trips
+    // overlap the sums of the tile totals below.
+    const bool mine = !abort && q < cnt;
+    const unsigned int kraw = mine ? kept[i0 + q] : 0u;
+    const unsigned int kq = kraw & ~kKeptLong;
+    const bool is_long = mine && (kraw & kKeptLong) != 0u;
+    const unsigned int sq = mine ? inv[i0 + q] : 0u;
+    // The bound only keeps a corrupted sorted row from reading outside the workspace.
+    const bool fixed = mine && kq > 0u && !is_long && static_cast<long long>(sq) < rows;
+    unsigned int v[kListCap];
+    if (fixed) {
+        const uint4 *l4 = reinterpret_cast<const uint4 *>(temp + static_cast<size_t>(sq) * kListCap);
+#pragma unroll
+        for (int c = 0; c < kListCap / 4; ++c) {
+            const uint4 w = l4[c];
+            v[4 * c] = w.x;
+            v[4 * c + 1] = w.y;
+            v[4 * c + 2] = w.z;
+            v[4 * c + 3] = w.w;
+        }
+    }
     unsigned long long pre = 0, tot = 0;
     if (!abort && tiles_kept <= kFlatTiles) {
         // Few tiles: the tile totals are summed directly.
         for (int t = threadIdx.x; t < tiles_kept; t += kPlaceBlock) {
-            const unsigned long long v = sums_kept[t];
-            tot += v;
-            if (t < b) pre += v;
+            const unsigned long long x = sums_kept[t];
+            tot += x;
+            if (t < b) pre += x;
         }
     } else if (!abort) {
         for (int t = threadIdx.x; t < groups_kept; t += kPlaceBlock) {
-            const unsigned long long v = sums_kept2[t];
-            tot += v;
-            if (t < g) pre += v;
+            const unsigned long long x = sums_kept2[t];
+            tot += x;
+            if (t < g) pre += x;
         }
         const int t = g * kKeptGroup + static_cast<int>(threadIdx.x);
         if (threadIdx.x < kKeptGroup && t < b) pre += sums_kept[t];
@@ -1248,45 +1278,39 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     pre = block_sum(pre, scratch);
     tot = block_sum(tot, scratch);
     const long long E = static_cast<long long>(tot);
-    const bool overflow = static_cast<unsigned long long>(E) > cap || ctr->heavy_top > heavy_cap;
-    if (b == 0) {
-        unsigned long long t = 0, sv = 0, cp = 0;
-        if (!abort)
-            for (int k = threadIdx.x; k < search_blocks; k += kPlaceBlock) {
-                t += tested[k];
-                sv += tested[kMaxSearchBlocks + k];
-                cp += capped_blk[k];
-            }
-        t = block_sum(t, scratch);
-        sv = block_sum(sv, scratch);
-        cp = block_sum(cp, scratch);
-        if (threadIdx.x == 0) {
-            const Plan P = plans[0];
-            Report rep;
-            rep.n_edges = E;
-            rep.tested = t;
-            rep.survived = sv;
-            rep.abort = abort ? 1 : 0;
-            rep.capped = static_cast<unsigned int>(cp);
-            rep.heavy = ctr->heavy_count;
-            rep.n_cells = P.n_cells;
-            for (int p = 0; p < kMaxAxes; ++p) {
-                rep.G[p] = P.G[p];
-                rep.c[p] = P.c[p];
-            }
-            *report = rep;
-            edge_off[n_events] = E;
-            edge_off[n_events + 1] = abort ? 2 : (overflow ? 3 : 0);
+    const bool overflow = static_cast<unsigned long long>(E) > cap;
+    if (b == 0 && threadIdx.x == 0) {
+        const Plan P = plans[0];
+        Report rep;
+        rep.n_edges = E;
+        rep.tested = abort ? 0ull : ctr->tested;
+        rep.survived = abort ? 0ull : ctr->survived;
+        rep.abort = abort ? 1 : 0;
+        rep.capped = abort ? 0u : ctr->capped;
+        rep.heavy = ctr->heavy_count;
+        rep.n_cells = P.n_cells;
+        for (int p = 0; p < kMaxAxes; ++p) {
+            rep.G[p] = P.G[p];
+            rep.c[p] = P.c[p];
         }
+        *report = rep;
+        edge_off[n_events] = E;
+        edge_off[n_events + 1] = abort ? 2 : (overflow ? 3 : 0);
     }
-    const long long i0 = static_cast<long long>(b) * kPlaceTile;
-    const int cnt = static_cast<int>(rows - i0 < kPlaceTile ? rows - i0 : kPlaceTile);
-    const int q = threadIdx.x;
-    const unsigned int kraw = (!abort && q < cnt) ? kept[i0 + q] : 0u;
-    const unsigned int kq = kraw & ~kKeptLong;
-    const unsigned int oq = static_cast<unsigned int>(block_exclusive_scan(kq, scratch));
-    if (q < cnt) o[q] = oq;
-    if (q == cnt - 1) o[cnt] = oq + kq;
+    // Offsets of the queries' edges in the block (low word) and the rank of each
+    // long list among the block's (high word).
+    const unsigned long long sx =
+        block_exclusive_scan((is_long ? 1ull << 32 : 0ull) | kq, scratch);
+    const unsigned int oq = static_cast<unsigned int>(sx);
+    if (q < cnt) {
+        o[q] = oq;
+        kind[q] = is_long ? 2 : (fixed ? 1 : 0);
+        if (is_long) long_q[sx >> 32] = static_cast<unsigned char>(q);
+    }
+    if (q == cnt - 1) {
+        o[cnt] = oq + kq;
+        n_long_s = static_cast<unsigned int>(sx >> 32) + (is_long ? 1u : 0u);
+    }
     __syncthreads();
     // Edge ranges of the events whose first row lies in this block (events with no
     // rows at the very end start at E).
@@ -1305,58 +1329,50 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
         }
     }
     if (abort || overflow) return;
-    // Where the query's list sits in temp: its sorted row's fixed place, or for a
-    // long list the place the long-list kernel chose.
-    unsigned long long tq = 0;
-    if (q < cnt) {
-        tq = (kraw & kKeptLong) ? tpos[i0 + q] : static_cast<unsigned long long>(inv[i0 + q]) * kListCap;
-        tp[q] = tq;
-        base_row[q] = n_events == 1 ? 0u : static_cast<unsigned int>(ev[find_event(ev, n_events, i0 + q)].row0);
-    }
+    if (q < cnt) base_row[q] = n_events == 1 ? 0u : static_cast<unsigned int>(ev[find_event(ev, n_events, i0 + q)].row0);
     const unsigned int total = o[cnt];
     if (pre + total > cap) return;  // cannot happen when E <= cap; never write past the outputs
-    // End of the fixed list places; long lists live after it.
-    const unsigned long long fixed_end = static_cast<unsigned long long>(rows) * kListCap;
+    const unsigned int n_long = n_long_s;
+    if (n_long) {
+        for (unsigned int h = 0; h < n_long; ++h) {
+            const int ql = long_q[h];
+            const long long gi = i0 + ql;
+            const unsigned int slot = inv[gi];
+            const int e = n_events == 1 ? 0 : find_event(ev, n_events, gi);
+            const Plan P = plans[e];
+            const unsigned int nq = o[ql + 1] - o[ql];
+            if (static_cast<long long>(slot) >= rows) continue;  // only a corrupted inverse
+            long_list<DP>(sorted, sorted_id, cell_start, P, static_cast<unsigned int>(ev[e].cell0), slot, r2, nq,
+                          nq == static_cast<unsigned int>(K), ev[e].row0, dst + pre + o[ql], staged, L);
+        }
+    }
     // Lists in the fixed places come from the search in the order their hits were
     // found: the query's thread sorts its list (a bitonic network over 16 slots, the
     // unused ones holding the largest value) and stages it in LDS.
-    if (q < cnt && kq > 0u) {
-        const unsigned long long t0 = tq;
-        if (t0 < fixed_end && t0 + kListCap <= temp_len) {
-            const uint4 *l4 = reinterpret_cast<const uint4 *>(temp + t0);
-            unsigned int v[kListCap];
+    if (fixed) {
 #pragma unroll
-            for (int c = 0; c < kListCap / 4; ++c) {
-                const uint4 w = l4[c];
-                v[4 * c] = w.x;
-                v[4 * c + 1] = w.y;
-                v[4 * c + 2] = w.z;
-                v[4 * c + 3] = w.w;
-            }
+        for (int u = 0; u < kListCap; ++u) v[u] = static_cast<unsigned int>(u) < kq ? v[u] : 0xffffffffu;
 #pragma unroll
-            for (int u = 0; u < kListCap; ++u) v[u] = static_cast<unsigned int>(u) < kq ? v[u] : 0xffffffffu;
+        for (int k = 2; k <= kListCap; k <<= 1) {
 #pragma unroll
-            for (int k = 2; k <= kListCap; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
-                for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-                    for (int u = 0; u < kListCap; ++u) {
-                        const int l = u ^ j;
-                        if (l > u) {
-                            const unsigned int lo = v[u] < v[l] ? v[u] : v[l];
-                            const unsigned int hi = v[u] < v[l] ? v[l] : v[u];
-                            const bool up = (u & k) == 0;
-                            v[u] = up ? lo : hi;
-                            v[l] = up ? hi : lo;
-                        }
+                for (int u = 0; u < kListCap; ++u) {
+                    const int l = u ^ j;
+                    if (l > u) {
+                        const unsigned int lo = v[u] < v[l] ? v[u] : v[l];
+                        const unsigned int hi = v[u] < v[l] ? v[l] : v[u];
+                        const bool up = (u & k) == 0;
+                        v[u] = up ? lo : hi;
+                        v[l] = up ? hi : lo;
                     }
                 }
             }
-            uint4 *st = reinterpret_cast<uint4 *>(staged + q * kListCap);
-#pragma unroll
-            for (int c = 0; c < kListCap / 4; ++c)
-                st[c] = make_uint4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
         }
+        uint4 *st = reinterpret_cast<uint4 *>(staged + q * kListCap);
+#pragma unroll
+        for (int c = 0; c < kListCap / 4; ++c)
+            st[c] = make_uint4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
     }
     __syncthreads();
     for (unsigned int w0 = 0; w0 < total; w0 += kOwnerWindow) {
@@ -1370,18 +1386,13 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
         for (unsigned int p = threadIdx.x; p < wend; p += kPlaceBlock) {
             const int r = owner[p];
             const unsigned int pos = w0 + p;
-            const unsigned int k = pos - o[r];
-            const unsigned long long t0 = tp[r];
             src[static_cast<long long>(pre) + pos] = i0 + r - base_row[r];
-            // The list positions come from the search; the bounds only keep a
-            // corrupted position from reading outside the workspace.
-            long long v = -1ll;
-            if (t0 < fixed_end) {
-                if (t0 + kListCap <= temp_len) v = static_cast<long long>(staged[r * kListCap + k]) - base_row[r];
-            } else if (t0 + k < temp_len) {
-                v = static_cast<long long>(temp[t0 + k]) - base_row[r];
-            }
-            dst[static_cast<long long>(pre) + pos] = v;
+            // Long lists are in place already; a query with neither kind of list
+            // (only a corrupted sorted row) gets -1.
+            const int kd = kind[r];
+            if (kd != 2)
+                dst[static_cast<long long>(pre) + pos] =
+                    kd == 1 ? static_cast<long long>(staged[r * kListCap + (pos - o[r])]) - base_row[r] : -1ll;
         }
         __syncthreads();
     }
@@ -1404,21 +1415,23 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     if (a.K < kListCap)
         hipLaunchKernelGGL((k_search<DP, true>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
                            ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
-                           a.r2, a.K, ws.kept, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
-                           a.search_prio);
+                           a.r2, a.K, ws.kept, ws.temp, ws.ctr, ws.tested, ws.capped_blk, a.search_prio);
     else
         hipLaunchKernelGGL((k_search<DP, false>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
                            ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
-                           a.r2, a.K, ws.kept, ws.temp, ws.heavy, ws.ctr, ws.tested, ws.capped_blk,
-                           a.search_prio);
+                           a.r2, a.K, ws.kept, ws.temp, ws.ctr, ws.tested, ws.capped_blk, a.search_prio);
     mark(5);
-    const unsigned long long heavy_base = static_cast<unsigned long long>(rows) * kListCap;
-    const long long hb = (static_cast<long long>(ws.tiles_kept_n) + kWaves - 1) / kWaves;
-    const int heavy_blocks = static_cast<int>(hb < kHeavyBlocks ? kHeavyBlocks : (hb > 2048 ? 2048 : hb));
-    hipLaunchKernelGGL(k_heavy<DP>, dim3(heavy_blocks), dim3(kBlock), 0, a.stream, ws.sorted, ws.sorted_id,
-                       ws.cell_start, ws.ev, ws.plans, a.r2, a.K, static_cast<int>(rows), ws.kept, ws.sums_kept,
-                       ws.sums_kept2, ws.tiles_kept_n, ws.tpos, ws.temp, heavy_base, a.edge_capacity, ws.heavy,
+    const long long kb = (static_cast<long long>(ws.tiles_kept_n) + kWaves - 1) / kWaves;
+    const int kblocks = static_cast<int>(kb > 2048 ? 2048 : kb);
+    hipLaunchKernelGGL(k_kept_sums, dim3(kblocks), dim3(kBlock), 0, a.stream, static_cast<int>(rows), ws.kept,
+                       ws.sums_kept, ws.sums_kept2, ws.tiles_kept_n, ws.tested, ws.capped_blk, a.search_blocks,
                        ws.ctr);
+    mark(6);
+    hipLaunchKernelGGL(k_place<DP>, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
+                       rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n,
+                       ws.tiles_kept_n, ws.inv, ws.temp, ws.sorted, ws.sorted_id, ws.cell_start, a.r2, a.K,
+                       a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, a.edge_off_out ? a.edge_off_out : ws.edge_off,
+                       a.report_out ? a.report_out : ws.report);
 }
 
 template <int DP>
@@ -1481,14 +1494,6 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
         case 48: launch_rows<48>(a, ws, vec4); break;
         default: launch_rows<64>(a, ws, vec4); break;
     }
-    mark(6);
-    hipLaunchKernelGGL(k_place, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
-                       ws.rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n,
-                       ws.tiles_kept_n, ws.tpos, ws.inv,
-                       ws.temp, static_cast<unsigned long long>(ws.rows) * kListCap + a.edge_capacity,
-                       a.edge_capacity, a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, ws.tested, ws.capped_blk,
-                       a.search_blocks, a.edge_off_out ? a.edge_off_out : ws.edge_off,
-                       a.report_out ? a.report_out : ws.report);
     mark(7);
     return hipGetLastError();
 }

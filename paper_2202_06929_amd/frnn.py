@@ -27,7 +27,7 @@ MAX_K = 4096
 NOALLOC_SCRATCH_MIB = 64
 FLAG_TIMING = 1
 FLAG_EVENTS_RESIDENT = 2
-STAGES = ("bounds", "keys", "cells", "scatter", "search", "long", "place")
+STAGES = ("bounds", "keys", "cells", "scatter", "search", "totals", "place")
 
 
 class FrnnError(RuntimeError):
@@ -46,7 +46,7 @@ class FrnnStats(ctypes.Structure):
                 ("n_cells", ctypes.c_int64), ("axes", ctypes.c_int32), ("grid", ctypes.c_int32 * 4),
                 ("dims", ctypes.c_int32 * 4), ("cell", ctypes.c_float * 4),
                 ("capped_queries", ctypes.c_int32), ("overflow_queries", ctypes.c_int32),
-                ("stage_ms", ctypes.c_float * 7), ("survivors", ctypes.c_int64)]
+                ("stage_ms", ctypes.c_float * len(STAGES)), ("survivors", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         a = self.axes
