@@ -652,6 +652,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     __shared__ __align__(16) unsigned int lst_all[kWaves][kQT * kListCap];
     __shared__ unsigned int lstd_all[SEL ? kWaves : 1][SEL ? kQT * kListCap : 1];  // D bits of each hit
     __shared__ unsigned long long thr_all[SEL ? kWaves : 1][SEL ? kQT : 1];       // K-th smallest (D, j) key
+    __shared__ unsigned int qorig_all[SEL ? kWaves : 1][SEL ? kQT : 1];           // original row of each query
     __shared__ unsigned int pre_all[kWaves][kQT + 1];
     __shared__ unsigned int cnt_all[kWaves][kQT];
     __shared__ unsigned int qcnt_all[kWaves][kQT];
@@ -667,6 +668,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned int *lst = lst_all[wave_id()];
     unsigned int *lstd = lstd_all[SEL ? wave_id() : 0];
     unsigned long long *thr = thr_all[SEL ? wave_id() : 0];
+    unsigned int *qorig = qorig_all[SEL ? wave_id() : 0];
     unsigned int capped = 0;
     unsigned int *tpre = pre_all[wave_id()];
     unsigned int *tcnt = cnt_all[wave_id()];
@@ -908,20 +910,21 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     __shfl(static_cast<int>(v_orig), static_cast<int>((q0 - win + lane) & 63u)));
                 wave_lds_sync();
                 // Kept counts for every query; lists that fit are stored at a fixed place
-                // (kListCap slots per sorted row), longer ones are collected again by the
-                // placement pass.
+                // (kListCap slots per original row), longer ones are collected again by
+                // the placement pass.
                 const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
                                   (SEL || cnt <= static_cast<unsigned int>(K));
                 if (lane < Qn) {
                     const unsigned int i = iq;
-                    // One scattered 4-byte store per query: a list that fits sits at its
-                    // sorted row's fixed place, which placement finds through inv.
+                    // Scattered stores (the count, then the list in 16-byte pieces) put
+                    // everything about query i at places indexed by i, which the placement
+                    // pass then reads in order.
                     const unsigned int kq = min(cnt, static_cast<unsigned int>(K));
                     kept[i] = kq | (fits ? 0u : kKeptLong);
                     if (cnt > static_cast<unsigned int>(K)) ++capped;
                     if (!fits) atomicAdd(&ctr->heavy_count, 1u);
                 }
-                // Lists that fit go to their fixed place (kListCap slots per sorted row)
+                // Lists that fit go to their fixed place (kListCap slots per original row)
                 // as found, in 16-byte pieces; the placement pass orders every such list
                 // by neighbour id.  With the cap binding (SEL and more than K hits), the
                 // entries of those lists are numbered through a prefix over their
@@ -932,7 +935,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 const unsigned int Ku = static_cast<unsigned int>(K);
                 if (fits && !(SEL && cnt > Ku)) {
                     const uint4 *from = reinterpret_cast<const uint4 *>(lst + lane * kListCap);
-                    uint4 *to = reinterpret_cast<uint4 *>(temp + static_cast<size_t>(q0 + lane) * kListCap);
+                    uint4 *to = reinterpret_cast<uint4 *>(temp + static_cast<size_t>(iq) * kListCap);
                     for (unsigned int k = 0; 4u * k < cnt; ++k) to[k] = from[k];
                 }
                 if (SEL) {
@@ -942,6 +945,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     if (lane < Qn) {
                         tpre[lane] = inc - take;
                         tcnt[lane] = take;
+                        qorig[lane] = iq;
                     }
                     wave_lds_sync();
                     auto entry_query = [&](unsigned int t) {
@@ -984,7 +988,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                 for (unsigned int u = 0; u < cq; ++u)
                                     rk += (l[u] < j && ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) <= lim)
                                               ? 1u : 0u;
-                                temp[static_cast<size_t>(q0 + lo) * kListCap + rk] = j;
+                                temp[static_cast<size_t>(qorig[lo]) * kListCap + rk] = j;
                             }
                         }
                     }
@@ -1195,14 +1199,14 @@ __device__ void long_list(const float *__restrict__ sorted, const unsigned int *
 // first output position is the sum of the kept totals before it (whole groups of
 // kKeptGroup tiles, then the tiles of its own group); a block scan of its kept
 // counts gives each query's offset.  Long lists of the block's queries are
-// collected again and written first, one at a time by the whole block.  Output
-// positions are then mapped to their query through an owner table in LDS, a
-// window at a time, so that consecutive threads write consecutive int64
-// positions.  Lists in the fixed kListCap-slot places come from the search in the
-// order their hits were found: each query's thread sorts its list in registers and
-// stages it in LDS first.  Indices are made local to each query's event.  Block 0
-// writes the report and the status; the block holding an event's first row writes
-// its edge offset.
+// collected again and written first, one at a time by the whole block.  Lists in
+// the fixed kListCap-slot places come from the search in the order their hits were
+// found: each query's thread sorts its list in registers.  The block's output is
+// then formed in LDS a window at a time (each query's thread puts its row and its
+// neighbours at its own positions), so that consecutive threads write consecutive
+// int64 positions.  Indices are made local to each query's event.  Block 0 writes
+// the report and the status; the block holding an event's first row writes its
+// edge offset.
 template <int DP>
 __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const EventDesc *__restrict__ ev,
                                                        int n_events, const unsigned int *__restrict__ kept,
@@ -1220,14 +1224,15 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                                                        long long *__restrict__ edge_off,
                                                        Report *__restrict__ report) {
     static_assert(kPlaceBlock == kPlaceTile && kPlaceTile <= 256, "one query per thread, owner ids fit a byte");
-    static_assert(kPlaceTile * kListCap >= kMaxK, "the staging array holds a long list");
+    static_assert(kOwnerWindow >= kMaxK, "a window's array holds a long list");
+    // A window of the block's output (event-local rows and neighbours); a
+    // neighbour entry of kSkip belongs to a long list, which is in place already.
+    constexpr unsigned int kSkip = 0xffffffffu;
     __shared__ unsigned int o[kPlaceTile + 1];
-    __shared__ unsigned int base_row[kPlaceTile];
-    __shared__ unsigned char owner[kOwnerWindow];
-    __shared__ unsigned char kind[kPlaceTile];    // 1: list at the fixed place, 2: long list, 0: none
+    __shared__ unsigned int wsrc[kOwnerWindow];
+    __shared__ unsigned int wdst[kOwnerWindow];
     __shared__ unsigned char long_q[kPlaceTile];  // the block's long-list queries, in order
     __shared__ unsigned int n_long_s;
-    __shared__ __align__(16) unsigned int staged[kPlaceTile * kListCap];  // sorted fixed-place lists
     __shared__ unsigned long long scratch[kWaves];
     __shared__ LongLds<DP> L;
     const bool abort = ctr->abort != 0;
@@ -1236,19 +1241,17 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     const long long i0 = static_cast<long long>(b) * kPlaceTile;
     const int cnt = static_cast<int>(rows - i0 < kPlaceTile ? rows - i0 : kPlaceTile);
     const int q = threadIdx.x;
-    // The query's kept count, its sorted row (whose fixed place holds a list of up
-    // to kListCap) and that list are requested first, so that their round trips
-    // overlap the sums of the tile totals below.
+    // The query's kept count and its list of up to kListCap (at the query's own
+    // fixed place) are requested first, so that their round trips overlap the sums
+    // of the tile totals below.
     const bool mine = !abort && q < cnt;
     const unsigned int kraw = mine ? kept[i0 + q] : 0u;
     const unsigned int kq = kraw & ~kKeptLong;
     const bool is_long = mine && (kraw & kKeptLong) != 0u;
-    const unsigned int sq = mine ? inv[i0 + q] : 0u;
-    // The bound only keeps a corrupted sorted row from reading outside the workspace.
-    const bool fixed = mine && kq > 0u && !is_long && static_cast<long long>(sq) < rows;
+    const bool fixed = mine && kq > 0u && !is_long;
     unsigned int v[kListCap];
     if (fixed) {
-        const uint4 *l4 = reinterpret_cast<const uint4 *>(temp + static_cast<size_t>(sq) * kListCap);
+        const uint4 *l4 = reinterpret_cast<const uint4 *>(temp + static_cast<size_t>(i0 + q) * kListCap);
 #pragma unroll
         for (int c = 0; c < kListCap / 4; ++c) {
             const uint4 w = l4[c];
@@ -1304,7 +1307,6 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     const unsigned int oq = static_cast<unsigned int>(sx);
     if (q < cnt) {
         o[q] = oq;
-        kind[q] = is_long ? 2 : (fixed ? 1 : 0);
         if (is_long) long_q[sx >> 32] = static_cast<unsigned char>(q);
     }
     if (q == cnt - 1) {
@@ -1329,26 +1331,25 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
         }
     }
     if (abort || overflow) return;
-    if (q < cnt) base_row[q] = n_events == 1 ? 0u : static_cast<unsigned int>(ev[find_event(ev, n_events, i0 + q)].row0);
+    const unsigned int brow =
+        n_events == 1 || q >= cnt ? 0u : static_cast<unsigned int>(ev[find_event(ev, n_events, i0 + q)].row0);
     const unsigned int total = o[cnt];
     if (pre + total > cap) return;  // cannot happen when E <= cap; never write past the outputs
     const unsigned int n_long = n_long_s;
-    if (n_long) {
-        for (unsigned int h = 0; h < n_long; ++h) {
-            const int ql = long_q[h];
-            const long long gi = i0 + ql;
-            const unsigned int slot = inv[gi];
-            const int e = n_events == 1 ? 0 : find_event(ev, n_events, gi);
-            const Plan P = plans[e];
-            const unsigned int nq = o[ql + 1] - o[ql];
-            if (static_cast<long long>(slot) >= rows) continue;  // only a corrupted inverse
-            long_list<DP>(sorted, sorted_id, cell_start, P, static_cast<unsigned int>(ev[e].cell0), slot, r2, nq,
-                          nq == static_cast<unsigned int>(K), ev[e].row0, dst + pre + o[ql], staged, L);
-        }
+    for (unsigned int h = 0; h < n_long; ++h) {
+        const int ql = long_q[h];
+        const long long gi = i0 + ql;
+        const unsigned int slot = inv[gi];
+        const int e = n_events == 1 ? 0 : find_event(ev, n_events, gi);
+        const Plan P = plans[e];
+        const unsigned int nq = o[ql + 1] - o[ql];
+        if (static_cast<long long>(slot) >= rows) continue;  // only a corrupted inverse
+        long_list<DP>(sorted, sorted_id, cell_start, P, static_cast<unsigned int>(ev[e].cell0), slot, r2, nq,
+                      nq == static_cast<unsigned int>(K), ev[e].row0, dst + pre + o[ql], wdst, L);
     }
-    // Lists in the fixed places come from the search in the order their hits were
-    // found: the query's thread sorts its list (a bitonic network over 16 slots, the
-    // unused ones holding the largest value) and stages it in LDS.
+    // A list from a fixed place holds the query's hits in the order they were found:
+    // its thread sorts it (a bitonic network over 16 slots, the unused ones holding
+    // the largest value).
     if (fixed) {
 #pragma unroll
         for (int u = 0; u < kListCap; ++u) v[u] = static_cast<unsigned int>(u) < kq ? v[u] : 0xffffffffu;
@@ -1369,30 +1370,33 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                 }
             }
         }
-        uint4 *st = reinterpret_cast<uint4 *>(staged + q * kListCap);
-#pragma unroll
-        for (int c = 0; c < kListCap / 4; ++c)
-            st[c] = make_uint4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
     }
-    __syncthreads();
+    const unsigned int il = static_cast<unsigned int>(i0 + q) - brow;  // the query's event-local row
     for (unsigned int w0 = 0; w0 < total; w0 += kOwnerWindow) {
         const unsigned int wend = total - w0 < kOwnerWindow ? total - w0 : kOwnerWindow;
-        if (q < cnt) {
+        if (fixed) {
+#pragma unroll
+            for (int u = 0; u < kListCap; ++u) {
+                const unsigned int pw = oq + static_cast<unsigned int>(u) - w0;  // wraps when before the window
+                if (static_cast<unsigned int>(u) < kq && oq + u >= w0 && pw < wend) {
+                    wsrc[pw] = il;
+                    wdst[pw] = v[u] - brow;
+                }
+            }
+        } else if (is_long) {
             const unsigned int a0 = oq > w0 ? oq - w0 : 0u;
             const unsigned int a1 = oq + kq > w0 ? min(oq + kq - w0, wend) : 0u;
-            for (unsigned int p = a0; p < a1; ++p) owner[p] = static_cast<unsigned char>(q);
+            for (unsigned int pw = a0; pw < a1; ++pw) {
+                wsrc[pw] = il;
+                wdst[pw] = kSkip;
+            }
         }
         __syncthreads();
-        for (unsigned int p = threadIdx.x; p < wend; p += kPlaceBlock) {
-            const int r = owner[p];
-            const unsigned int pos = w0 + p;
-            src[static_cast<long long>(pre) + pos] = i0 + r - base_row[r];
-            // Long lists are in place already; a query with neither kind of list
-            // (only a corrupted sorted row) gets -1.
-            const int kd = kind[r];
-            if (kd != 2)
-                dst[static_cast<long long>(pre) + pos] =
-                    kd == 1 ? static_cast<long long>(staged[r * kListCap + (pos - o[r])]) - base_row[r] : -1ll;
+        for (unsigned int pw = threadIdx.x; pw < wend; pw += kPlaceBlock) {
+            const long long at = static_cast<long long>(pre) + w0 + pw;
+            src[at] = wsrc[pw];
+            const unsigned int dv = wdst[pw];
+            if (dv != kSkip) dst[at] = dv;
         }
         __syncthreads();
     }
