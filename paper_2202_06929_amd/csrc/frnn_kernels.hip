@@ -477,7 +477,9 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
 // ------------------------------------------------------------------- scans
 
 // out[i] = sum of in[0..i) for i in [0, len]; out[len] is the total.  sums[t] holds
-// the total of tile t (kScanTile elements).
+// the total of tile t (kScanTile elements).  The tile's elements are requested
+// before the totals of the tiles before it are summed, so that the two round
+// trips overlap.
 template <typename OutT>
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__restrict__ in, long long len,
                                                        const unsigned long long *__restrict__ sums,
@@ -485,19 +487,20 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__res
     __shared__ unsigned long long scratch[kWaves];
     const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
     if (base > len) return;
-    unsigned long long off = 0;
-    for (unsigned int t = threadIdx.x; t < blockIdx.x; t += kBlock) off += sums[t];
-    off = block_sum(off, scratch);
     constexpr int kPer = kScanTile / kBlock;
     unsigned int v[kPer];
-    unsigned long long tsum = 0;
     const long long first = base + static_cast<long long>(threadIdx.x) * kPer;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const long long idx = first + j;
         v[j] = idx < len ? in[idx] : 0u;
-        tsum += v[j];
     }
+    unsigned long long off = 0;
+    for (unsigned int t = threadIdx.x; t < blockIdx.x; t += kBlock) off += sums[t];
+    off = block_sum(off, scratch);
+    unsigned long long tsum = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) tsum += v[j];
     unsigned long long run = block_exclusive_scan(tsum, scratch) + off;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -1026,8 +1029,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
 
 // Totals of the kept counts per placement tile, one wave per tile, and per group
 // of kKeptGroup tiles (spread-address atomics into totals cleared by the bounds
-// pass).  Block 0 also sums the search's per-workgroup counts for the report,
-// off the placement pass's critical path.
+// pass).  The last workgroup, which has no tiles, sums the search's per-workgroup
+// counts for the report, beside the others and off the placement pass's path.
 __global__ __launch_bounds__(kBlock) void k_kept_sums(int n, const unsigned int *__restrict__ kept,
                                                       unsigned long long *__restrict__ sums_kept,
                                                       unsigned long long *__restrict__ sums_kept2, int tiles_kept,
@@ -1035,24 +1038,37 @@ __global__ __launch_bounds__(kBlock) void k_kept_sums(int n, const unsigned int 
                                                       const unsigned int *__restrict__ capped_blk,
                                                       int search_blocks, Counters *__restrict__ ctr) {
     if (ctr->abort) return;
-    if (blockIdx.x == 0) {
-        __shared__ unsigned long long red[kWaves];
+    if (blockIdx.x == gridDim.x - 1) {
+        __shared__ unsigned long long red[3][kWaves];
         unsigned long long t = 0, sv = 0, cp = 0;
         for (int k = threadIdx.x; k < search_blocks; k += kBlock) {
             t += tested[k];
             sv += tested[kMaxSearchBlocks + k];
             cp += capped_blk[k];
         }
-        t = block_sum(t, red);
-        sv = block_sum(sv, red);
-        cp = block_sum(cp, red);
+        t = wave_sum(t);
+        sv = wave_sum(sv);
+        cp = wave_sum(cp);
+        if (lane_id() == 0) {
+            red[0][wave_id()] = t;
+            red[1][wave_id()] = sv;
+            red[2][wave_id()] = cp;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
+            t = sv = cp = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                t += red[0][w];
+                sv += red[1][w];
+                cp += red[2][w];
+            }
             ctr->tested = t;
             ctr->survived = sv;
             ctr->capped = static_cast<unsigned int>(cp);
         }
+        return;
     }
-    const int nw = static_cast<int>(gridDim.x) * kWaves;
+    const int nw = static_cast<int>(gridDim.x - 1) * kWaves;
     for (int t = static_cast<int>(blockIdx.x) * kWaves + wave_id(); t < tiles_kept; t += nw) {
         const long long b = static_cast<long long>(t) * kPlaceTile;
         unsigned long long s = 0;
@@ -1426,7 +1442,7 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
                            a.r2, a.K, ws.kept, ws.temp, ws.ctr, ws.tested, ws.capped_blk, a.search_prio);
     mark(5);
     const long long kb = (static_cast<long long>(ws.tiles_kept_n) + kWaves - 1) / kWaves;
-    const int kblocks = static_cast<int>(kb > 2048 ? 2048 : kb);
+    const int kblocks = static_cast<int>(kb > 2048 ? 2048 : kb) + 1;  // and one for the search's counts
     hipLaunchKernelGGL(k_kept_sums, dim3(kblocks), dim3(kBlock), 0, a.stream, static_cast<int>(rows), ws.kept,
                        ws.sums_kept, ws.sums_kept2, ws.tiles_kept_n, ws.tested, ws.capped_blk, a.search_blocks,
                        ws.ctr);
