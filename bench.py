@@ -397,7 +397,7 @@ def batched_bench(steps: int, warmup: int, log) -> dict:
     # Plain loop: one call (and one synchronisation) per event.
     views = [pts[int(offsets[k]):int(offsets[k + 1])] for k in range(len(sizes))]
     caps = [16 * n for n in sizes]
-    wss = [torch.empty(frnn.workspace_bytes(n, d, c), dtype=torch.uint8, device=dev) for n, c in zip(sizes, caps)]
+    wss = [torch.empty(frnn.workspace_bytes(n, d), dtype=torch.uint8, device=dev) for n in sizes]
     outs = [torch.empty((2, c), dtype=torch.int64, device=dev) for c in caps]
     alone = []
     for k in range(len(sizes)):
@@ -420,7 +420,7 @@ def batched_bench(steps: int, warmup: int, log) -> dict:
     # One batched call, then a captured graph of the same batch replayed.
     total_e = sum(a.shape[1] for a in alone)
     cap = total_e + 4096
-    ws = torch.empty(frnn.batch_workspace_bytes(offsets, d, cap), dtype=torch.uint8, device=dev)
+    ws = torch.empty(frnn.batch_workspace_bytes(offsets, d), dtype=torch.uint8, device=dev)
     out = torch.empty((2, cap), dtype=torch.int64, device=dev)
     st, eo = frnn.build_batch_into(pts, offsets, r, K, ws, out[0], out[1], cfg)
     assert st == frnn.FRNN_OK and eo[-1] == total_e
@@ -641,7 +641,7 @@ def main():
     cfg = frnn.Config(cell_div=args.cell_div or 1, axes=args.axes)
     cap = 16 * n
     offs = np.array([0, n], dtype=np.int64)
-    ws = torch.empty(max(frnn.workspace_bytes(n, d, cap), frnn.batch_workspace_bytes(offs, d, cap)),
+    ws = torch.empty(max(frnn.workspace_bytes(n, d), frnn.batch_workspace_bytes(offs, d)),
                      dtype=torch.uint8, device=dev)
     out = torch.empty((2, cap), dtype=torch.int64, device=dev)
 

@@ -117,17 +117,16 @@ typedef struct frnn_stats {
                                    that the search added the remaining terms of the distance */
 } frnn_stats;
 
-/* Bytes of device workspace frnn_build needs for n points of dimension d (the
- * size does not depend on edge_capacity, which is only checked).  Host-only
- * arithmetic; returns 0 for invalid arguments (n < 0, d outside [3, 64],
- * edge_capacity < 0). */
-size_t frnn_workspace_bytes(int64_t n, int32_t d, int64_t edge_capacity);
+/* Bytes of device workspace frnn_build needs for n points of dimension d.
+ * Host-only arithmetic; returns 0 for invalid arguments (n outside [0, 2^31),
+ * d outside [3, 64]). */
+size_t frnn_workspace_bytes(int64_t n, int32_t d);
 
 /* Builds the FRNN graph of the points.
  *   points          device, float32, row-major [n, d] (row i at points + i*d)
  *   n, d            point count (0 <= n < 2^31) and dimension (3 <= d <= 64)
  *   r, K            radius (finite, > 0) and cap (1 <= K <= FRNN_MAX_K)
- *   workspace       device scratch of at least frnn_workspace_bytes(n, d, edge_capacity)
+ *   workspace       device scratch of at least frnn_workspace_bytes(n, d)
  *                   bytes, 256-byte aligned; its contents on entry do not matter
  *   src, dst        device, int64 [edge_capacity] each: edge e is (src[e], dst[e]),
  *                   src the query i, dst the neighbour j, sorted by (i, j)
@@ -154,7 +153,7 @@ int frnn_build(const float *points, int64_t n, int32_t d, float r, int32_t K,
  * device looks the array up; later calls only enqueue kernels and copy the
  * report back.
  *   Arguments as for frnn_build, without workspace / workspace_bytes.
- *   FRNN_ERR_WORKSPACE     frnn_workspace_bytes(n, d, edge_capacity) exceeds the array
+ *   FRNN_ERR_WORKSPACE     frnn_workspace_bytes(n, d) exceeds the array
  *                          (checked on the host before any device work; for example
  *                          120,000 points of d = 8 with room for 16 edges per point fit)
  *   FRNN_ERR_ARG           also for FRNN_FLAG_TIMING (timing would create HIP events)
@@ -167,10 +166,8 @@ int frnn_build_noalloc(const float *points, int64_t n, int32_t d, float r, int32
                        const frnn_config *config, frnn_stats *stats, void *stream);
 
 /* Bytes of device workspace frnn_build_batch needs for the given events (see
- * below); edge_capacity is only checked.  Returns 0 for invalid
- * arguments. */
-size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events, int32_t d,
-                                  int64_t edge_capacity);
+ * below).  Returns 0 for invalid arguments. */
+size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events, int32_t d);
 
 /* Builds the FRNN graphs of several independent events in one pass (one launch
  * sequence and one synchronisation for the whole batch).  Each event is searched

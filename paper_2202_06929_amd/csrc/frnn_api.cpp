@@ -380,17 +380,16 @@ void init_stats(frnn_stats *stats, const frnn_config *config, int d) {
 
 }  // namespace
 
-extern "C" size_t frnn_workspace_bytes(int64_t n, int32_t d, int64_t edge_capacity) {
-    if (n < 0 || n >= (int64_t{1} << 31) || d < 3 || d > FRNN_MAX_D || edge_capacity < 0) return 0;
+extern "C" size_t frnn_workspace_bytes(int64_t n, int32_t d) {
+    if (n < 0 || n >= (int64_t{1} << 31) || d < 3 || d > FRNN_MAX_D) return 0;
     const int64_t offs[2] = {0, n};
     return layout(nullptr, n, describe_events(offs, 1, nullptr), 1, d).total_bytes;
 }
 
-extern "C" size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events, int32_t d,
-                                             int64_t edge_capacity) {
+extern "C" size_t frnn_batch_workspace_bytes(const int64_t *event_offsets, int32_t n_events, int32_t d) {
     long long rows = 0, cells = 0;
     int max_n = 0;
-    if (d < 3 || d > FRNN_MAX_D || edge_capacity < 0) return 0;
+    if (d < 3 || d > FRNN_MAX_D) return 0;
     if (check_events(event_offsets, n_events, &rows, &max_n, &cells) != FRNN_OK) return 0;
     return layout(nullptr, rows, cells, n_events, d).total_bytes;
 }
@@ -421,7 +420,7 @@ extern "C" int frnn_build(const float *points, int64_t n, int32_t d, float r, in
     if (n == 0) return FRNN_OK;
     if (!points || !workspace || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return FRNN_ERR_ARG;
-    if (workspace_bytes < frnn_workspace_bytes(n, d, edge_capacity)) return FRNN_ERR_WORKSPACE;
+    if (workspace_bytes < frnn_workspace_bytes(n, d)) return FRNN_ERR_WORKSPACE;
     const int64_t offs[2] = {0, n};
     EventDesc desc;
     const long long cells = describe_events(offs, 1, &desc);
@@ -576,7 +575,7 @@ extern "C" int frnn_build_noalloc(const float *points, int64_t n, int32_t d, flo
     *n_edges = 0;
     if (n == 0) return FRNN_OK;
     if (!points || (edge_capacity > 0 && (!src || !dst))) return FRNN_ERR_ARG;
-    if (frnn_workspace_bytes(n, d, edge_capacity) > kNoAllocBytes) return FRNN_ERR_WORKSPACE;
+    if (frnn_workspace_bytes(n, d) > kNoAllocBytes) return FRNN_ERR_WORKSPACE;
     void *workspace = nullptr;
     const int sw = noalloc_workspace(&workspace);
     if (sw != FRNN_OK) return sw;

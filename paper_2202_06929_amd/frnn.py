@@ -89,7 +89,7 @@ _lib = None
 def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     lib.frnn_workspace_bytes.restype = ctypes.c_size_t
-    lib.frnn_workspace_bytes.argtypes = [i64, i32, i64]
+    lib.frnn_workspace_bytes.argtypes = [i64, i32]
     lib.frnn_build.restype = ctypes.c_int
     lib.frnn_build.argtypes = [vp, i64, i32, ctypes.c_float, i32, vp, ctypes.c_size_t, vp, vp, i64,
                                ctypes.POINTER(i64), ctypes.POINTER(FrnnConfig),
@@ -98,7 +98,7 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.frnn_build_noalloc.argtypes = [vp, i64, i32, ctypes.c_float, i32, vp, vp, i64, ctypes.POINTER(i64),
                                        ctypes.POINTER(FrnnConfig), ctypes.POINTER(FrnnStats), vp]
     lib.frnn_batch_workspace_bytes.restype = ctypes.c_size_t
-    lib.frnn_batch_workspace_bytes.argtypes = [ctypes.POINTER(i64), i32, i32, i64]
+    lib.frnn_batch_workspace_bytes.argtypes = [ctypes.POINTER(i64), i32, i32]
     lib.frnn_build_batch.restype = ctypes.c_int
     lib.frnn_build_batch.argtypes = [vp, ctypes.POINTER(i64), i32, i32, ctypes.c_float, i32, vp, ctypes.c_size_t,
                                      vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(FrnnConfig),
@@ -137,8 +137,8 @@ def status_string(status: int) -> str:
     return lib().frnn_status_string(status).decode()
 
 
-def workspace_bytes(n: int, d: int, edge_capacity: int) -> int:
-    return int(lib().frnn_workspace_bytes(n, d, edge_capacity))
+def workspace_bytes(n: int, d: int) -> int:
+    return int(lib().frnn_workspace_bytes(n, d))
 
 
 def _stream_handle(device: torch.device) -> int:
@@ -185,7 +185,7 @@ def build(points: torch.Tensor, r: float, K: int, config: Config | None = None,
     cap = max(1, int(capacity)) if capacity is not None else max(1024, 16 * n)
     stats = FrnnStats()
     for attempt in range(2):
-        wsb = workspace_bytes(n, d, cap)
+        wsb = workspace_bytes(n, d)
         if wsb == 0:
             raise FrnnError(FRNN_ERR_ARG, "invalid sizes")
         ws = torch.empty(wsb, dtype=torch.uint8, device=points.device)
@@ -225,10 +225,10 @@ def _offsets_array(offsets) -> np.ndarray:
     return off
 
 
-def batch_workspace_bytes(offsets, d: int, edge_capacity: int) -> int:
+def batch_workspace_bytes(offsets, d: int) -> int:
     off = _offsets_array(offsets)
     return int(lib().frnn_batch_workspace_bytes(off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                                off.size - 1, d, edge_capacity))
+                                                off.size - 1, d))
 
 
 def build_batch_into(points: torch.Tensor, offsets, r: float, K: int, workspace: torch.Tensor,
@@ -264,7 +264,7 @@ def build_batch(points: torch.Tensor, offsets, r: float, K: int, config: Config 
     cap = max(1, int(capacity)) if capacity is not None else max(1024, 16 * rows)
     stats = FrnnStats()
     for attempt in range(2):
-        wsb = batch_workspace_bytes(off, d, cap)
+        wsb = batch_workspace_bytes(off, d)
         if wsb == 0:
             raise FrnnError(FRNN_ERR_ARG, "invalid sizes")
         ws = torch.empty(wsb, dtype=torch.uint8, device=points.device)

@@ -279,7 +279,7 @@ class GpuExecutor:
     def footprint(self, req: Request) -> int:
         n = max(req.n, 1)
         offs = np.array([0, n], dtype=np.int64)
-        return int(self.frnn.batch_workspace_bytes(offs, self.d, self.epp * n)) + 16 * self.epp * n
+        return int(self.frnn.batch_workspace_bytes(offs, self.d)) + 16 * self.epp * n
 
     def admit(self, req: Request) -> None:
         pass
@@ -297,7 +297,7 @@ class GpuExecutor:
         cap = max(1024, self.epp * rows)
         s.wait_stream(torch.cuda.current_stream(self.device))  # the points were produced there
         with torch.cuda.stream(s):
-            ws = torch.empty(frnn.batch_workspace_bytes(offsets, self.d, cap), dtype=torch.uint8, device=self.device)
+            ws = torch.empty(frnn.batch_workspace_bytes(offsets, self.d), dtype=torch.uint8, device=self.device)
             out = torch.empty((2, cap), dtype=torch.int64, device=self.device)
             eo = torch.empty(len(batch) + 2, dtype=torch.int64, device=self.device)
             if rows > 0:

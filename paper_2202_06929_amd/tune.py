@@ -88,7 +88,7 @@ def tune(points: torch.Tensor, offsets, r: float, K: int, repeats: int = 5,
     first = cands or candidates(d)
     _, eo0 = frnn.build_batch(points, off, r, K, config=first[0])
     cap = int(eo0[-1]) + 1024
-    ws_bytes = max(frnn.batch_workspace_bytes(off, d, cap), 1)
+    ws_bytes = max(frnn.batch_workspace_bytes(off, d), 1)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=points.device)
     out = torch.empty((2, cap), dtype=torch.int64, device=points.device)
     ref = {}

@@ -53,13 +53,12 @@ def test_status_strings(lib):
 
 def test_workspace_bytes_is_monotone_and_rejects_bad_sizes(lib):
     from paper_2202_06929_amd import frnn
-    a = frnn.workspace_bytes(1000, 8, 0)
+    a = frnn.workspace_bytes(1000, 8)
     assert a > 0
-    assert frnn.workspace_bytes(2000, 8, 0) > a
-    assert frnn.workspace_bytes(1000, 8, 10 ** 9) == a  # edges go straight to the outputs
-    assert frnn.workspace_bytes(1000, 12, 0) > a
-    for n, d, cap in ((-1, 8, 0), (10, 2, 0), (10, 65, 0), (10, 8, -1), (2 ** 31, 8, 0)):
-        assert frnn.workspace_bytes(n, d, cap) == 0
+    assert frnn.workspace_bytes(2000, 8) > a
+    assert frnn.workspace_bytes(1000, 12) > a
+    for n, d in ((-1, 8), (10, 2), (10, 65), (2 ** 31, 8)):
+        assert frnn.workspace_bytes(n, d) == 0
 
 
 def _call(lib, points=0, n=10, d=8, r=0.1, K=4, ws=0, wsb=0, src=0, dst=0, cap=0, cfg=None, E=True):
@@ -144,12 +143,10 @@ def test_noalloc_checks_return_before_touching_a_device(lib):
     # Sizes beyond the library's fixed array are refused on the host.
     limit = frnn.NOALLOC_SCRATCH_MIB << 20
     n_fit = 120_000
-    assert frnn.workspace_bytes(n_fit, 8, 16 * n_fit) <= limit
+    assert frnn.workspace_bytes(n_fit, 8) <= limit
     n_big = 1_000_000
-    assert frnn.workspace_bytes(n_big, 8, 0) > limit
+    assert frnn.workspace_bytes(n_big, 8) > limit
     assert _noalloc_call(lib, points=0x1000, n=n_big)[0] == frnn.FRNN_ERR_WORKSPACE
-    # The edge capacity does not count against the array: edges go straight to the outputs.
-    assert frnn.workspace_bytes(1000, 64, limit) == frnn.workspace_bytes(1000, 64, 0) <= limit
 
 
 def _batch_call(lib, offsets, n_events=None, d=8, r=0.1, K=4, ws=0, wsb=0, cap=0, eo=True):
@@ -176,12 +173,12 @@ def test_batch_argument_errors_and_workspace_sizes(lib):
     assert _batch_call(lib, [0, 0, 0]) == frnn.FRNN_OK  # no rows: nothing to do
     assert _batch_call(lib, [0, 10, 20]) == ERR         # null points and workspace
     assert _batch_call(lib, [0, 10, 20], ws=0x100000, wsb=16) == ERR  # points still null
-    one = frnn.batch_workspace_bytes([0, 1000], 8, 100)
-    assert one == frnn.workspace_bytes(1000, 8, 100)
-    two = frnn.batch_workspace_bytes([0, 1000, 3000], 8, 100)
-    assert two > frnn.batch_workspace_bytes([0, 2000], 8, 100) - 1 > one
-    assert frnn.batch_workspace_bytes([0, 5, 3], 8, 0) == 0
-    assert frnn.batch_workspace_bytes([0, 2 ** 31], 8, 0) == 0
+    one = frnn.batch_workspace_bytes([0, 1000], 8)
+    assert one == frnn.workspace_bytes(1000, 8)
+    two = frnn.batch_workspace_bytes([0, 1000, 3000], 8)
+    assert two > frnn.batch_workspace_bytes([0, 2000], 8) - 1 > one
+    assert frnn.batch_workspace_bytes([0, 5, 3], 8) == 0
+    assert frnn.batch_workspace_bytes([0, 2 ** 31], 8) == 0
 
 
 def test_distance_kernels_use_no_fused_or_packed_float_ops(tmp_path):

@@ -121,7 +121,7 @@ def test_capacity_error_reports_the_needed_count_and_retry_succeeds():
     pts = torch.from_numpy(X).to(DEV)
     n, d = X.shape
     cap = 100
-    ws = torch.empty(frnn.workspace_bytes(n, d, cap), dtype=torch.uint8, device=DEV)
+    ws = torch.empty(frnn.workspace_bytes(n, d), dtype=torch.uint8, device=DEV)
     out = torch.empty((2, cap), dtype=torch.int64, device=DEV)
     st, E = frnn.build_into(pts, spec.r, spec.K, ws, out[0], out[1])
     assert st == frnn.FRNN_ERR_CAPACITY and E == want.shape[1]
@@ -221,7 +221,7 @@ def test_captured_batch_graph_replays_match_eager():
     edges, eo = frnn.build_batch(pts, offsets, 0.1, 64)
     eager = edges.cpu().numpy()
     cap = int(eo[-1]) + 100
-    ws = torch.empty(frnn.batch_workspace_bytes(offsets, 8, cap), dtype=torch.uint8, device=DEV)
+    ws = torch.empty(frnn.batch_workspace_bytes(offsets, 8), dtype=torch.uint8, device=DEV)
     out = torch.empty((2, cap), dtype=torch.int64, device=DEV)
     eo_dev = torch.zeros(len(evs) + 2, dtype=torch.int64, device=DEV)
     assert frnn.build_batch_async(pts, offsets, 0.1, 64, ws, out[0], out[1], eo_dev) == frnn.FRNN_OK
@@ -249,7 +249,7 @@ def test_events_entry_point_matches_oracle():
     offsets = np.concatenate([[0], np.cumsum([len(x) for x in evs])]).astype(np.int64)
     want = [oracle.frnn_grid(X, 0.1, 64) for X in evs]
     cap = sum(w.shape[1] for w in want) + 64
-    ws = torch.empty(frnn.batch_workspace_bytes(offsets, 8, cap), dtype=torch.uint8, device=DEV)
+    ws = torch.empty(frnn.batch_workspace_bytes(offsets, 8), dtype=torch.uint8, device=DEV)
     out = torch.full((2, cap), -7, dtype=torch.int64, device=DEV)
     eo = torch.full((len(evs) + 2,), -1, dtype=torch.int64, device=DEV)
     log(f"events entry point: {len(evs)} events")
@@ -312,7 +312,7 @@ def test_nearest_eight_on_the_single_event():
     pts = torch.from_numpy(X).to(DEV)
     stats = frnn.FrnnStats()
     cap = 16 * spec.n
-    ws = torch.empty(frnn.workspace_bytes(spec.n, spec.d, cap), dtype=torch.uint8, device=DEV)
+    ws = torch.empty(frnn.workspace_bytes(spec.n, spec.d), dtype=torch.uint8, device=DEV)
     out = torch.empty((2, cap), dtype=torch.int64, device=DEV)
     st, E = frnn.build_into(pts, spec.r, spec.K, ws, out[0], out[1], None, stats)
     assert st == frnn.FRNN_OK

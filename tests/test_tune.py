@@ -49,7 +49,7 @@ def stub(monkeypatch):
         lib = StubLibrary(cost, wrong)
         monkeypatch.setattr(frnn, "build_batch_into", lib.build_batch_into)
         monkeypatch.setattr(frnn, "build_batch", lib.build_batch)
-        monkeypatch.setattr(frnn, "batch_workspace_bytes", lambda off, d, cap: 4096)
+        monkeypatch.setattr(frnn, "batch_workspace_bytes", lambda off, d: 4096)
         monkeypatch.setattr(tune, "_arch", lambda: "stub")
         monkeypatch.setattr(tune, "_sync", lambda: None)
         return lib

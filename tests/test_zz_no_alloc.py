@@ -27,7 +27,7 @@ def log(msg):
 
 def with_workspace(pts, r, K, cap):
     n, d = pts.shape
-    ws = torch.full((frnn.workspace_bytes(n, d, cap),), 0xA5, dtype=torch.uint8, device=DEV)
+    ws = torch.full((frnn.workspace_bytes(n, d),), 0xA5, dtype=torch.uint8, device=DEV)
     out = torch.full((2, cap), -7, dtype=torch.int64, device=DEV)
     stats = frnn.FrnnStats()
     st, E = frnn.build_into(pts, r, K, ws, out[0], out[1], stats=stats)
