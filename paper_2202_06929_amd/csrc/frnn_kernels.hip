@@ -103,25 +103,6 @@ __device__ __forceinline__ void load_row(const float *__restrict__ sorted, unsig
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-// Inclusive prefix sum across the 64 lanes of a wave.
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_scan(T v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        T u = __shfl_up(v, o);
-        if (lane >= o) v += u;
-    }
-    return v;
-}
-
 // Cross-lane steps with DPP (GFX9 encodings): row_shr:n moves lane i - n of the
 // same 16-lane row into lane i (0 when that lane is in another row); row_bcast:15
 // gives the rows selected by the row mask lane 15 of the row before; row_bcast:31
@@ -131,12 +112,26 @@ __device__ __forceinline__ unsigned int dpp_move(unsigned int v) {
     return static_cast<unsigned int>(
         __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, ROW_MASK, 0xf, true));
 }
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ unsigned long long dpp_move(unsigned long long v) {
+    const unsigned int lo = dpp_move<CTRL, ROW_MASK>(static_cast<unsigned int>(v));
+    const unsigned int hi = dpp_move<CTRL, ROW_MASK>(static_cast<unsigned int>(v >> 32));
+    return static_cast<unsigned long long>(hi) << 32 | lo;
+}
+// The same moves for a min/max fold: lanes without a source keep their own value.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_keep(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xf,
+                                                      false));
+}
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
 constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
 
 // Inclusive prefix sum across the 64 lanes (a scan within each row of 16 lanes,
-// then the row totals carried into the rows after them).
-__device__ __forceinline__ unsigned int wave_scan_add(unsigned int x) {
+// then the row totals carried into the rows after them), for 32- or 64-bit
+// unsigned values.
+template <typename T>
+__device__ __forceinline__ T wave_scan_add(T x) {
     x += dpp_move<kRowShr1>(x);
     x += dpp_move<kRowShr2>(x);
     x += dpp_move<kRowShr4>(x);
@@ -156,6 +151,49 @@ __device__ __forceinline__ unsigned int wave_scan_max(unsigned int x) {
     x = max(x, dpp_move<kRowBcast31, 0xc>(x));
     return x;
 }
+
+// Value of lane 63 in every lane.
+__device__ __forceinline__ unsigned int lane63(unsigned int x) { return __builtin_amdgcn_readlane(x, 63); }
+__device__ __forceinline__ unsigned long long lane63(unsigned long long x) {
+    return static_cast<unsigned long long>(__builtin_amdgcn_readlane(static_cast<unsigned int>(x >> 32), 63)) << 32 |
+           __builtin_amdgcn_readlane(static_cast<unsigned int>(x), 63);
+}
+__device__ __forceinline__ float lane63(float x) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// Sum over the 64 lanes, in every lane (32- or 64-bit unsigned).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    return lane63(wave_scan_add(v));
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    return wave_scan_add(v);
+}
+
+// Minimum and maximum over the 64 lanes, in every lane.
+__device__ __forceinline__ float wave_min(float x) {
+    x = fminf(x, dpp_keep<kRowShr1>(x));
+    x = fminf(x, dpp_keep<kRowShr2>(x));
+    x = fminf(x, dpp_keep<kRowShr4>(x));
+    x = fminf(x, dpp_keep<kRowShr8>(x));
+    x = fminf(x, dpp_keep<kRowBcast15, 0xa>(x));
+    x = fminf(x, dpp_keep<kRowBcast31, 0xc>(x));
+    return lane63(x);
+}
+__device__ __forceinline__ float wave_max(float x) {
+    x = fmaxf(x, dpp_keep<kRowShr1>(x));
+    x = fmaxf(x, dpp_keep<kRowShr2>(x));
+    x = fmaxf(x, dpp_keep<kRowShr4>(x));
+    x = fmaxf(x, dpp_keep<kRowShr8>(x));
+    x = fmaxf(x, dpp_keep<kRowBcast15, 0xa>(x));
+    x = fmaxf(x, dpp_keep<kRowBcast31, 0xc>(x));
+    return lane63(x);
+}
+__device__ __forceinline__ int wave_any(int x) { return __builtin_amdgcn_ballot_w64(x != 0) != 0ull ? 1 : 0; }
 
 // Sum over the block; every thread gets the total.
 __device__ unsigned long long block_sum(unsigned long long v, unsigned long long *scratch) {
@@ -240,28 +278,26 @@ __global__ __launch_bounds__(kBlock) void k_bounds(int d, Dims dd,
         const long long nv = total / 4;
         const int step = static_cast<int>((4ll * stride) % d);
         int col = static_cast<int>((4ll * tid) % d);
-        long long v = tid;
-        // Four independent loads in flight per thread.
-        for (; v + 3ll * stride < nv; v += 4ll * stride) {
+        // Four independent loads in flight per thread, issued together also for the
+        // last, partial round (the grid gives most threads exactly four), so that a
+        // thread waits for one round trip per four loads.
+        for (long long v = tid; v < nv; v += 4ll * stride) {
             float4 x[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) x[u] = X4[v + u * static_cast<long long>(stride)];
+            for (int u = 0; u < 4; ++u) {
+                const long long w = v + u * static_cast<long long>(stride);
+                x[u] = w < nv ? X4[w] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                acc.add(x[u].x, col, dd);
-                acc.add(x[u].y, col + 1, dd);
-                acc.add(x[u].z, col + 2, dd);
-                acc.add(x[u].w, col + 3, dd);
+                if (v + u * static_cast<long long>(stride) < nv) {
+                    acc.add(x[u].x, col, dd);
+                    acc.add(x[u].y, col + 1, dd);
+                    acc.add(x[u].z, col + 2, dd);
+                    acc.add(x[u].w, col + 3, dd);
+                }
                 col = next_col(col, step);
             }
-        }
-        for (; v < nv; v += stride) {
-            const float4 x = X4[v];
-            acc.add(x.x, col, dd);
-            acc.add(x.y, col + 1, dd);
-            acc.add(x.z, col + 2, dd);
-            acc.add(x.w, col + 3, dd);
-            col = next_col(col, step);
         }
     } else {
         const int step = stride % d;
@@ -272,13 +308,11 @@ __global__ __launch_bounds__(kBlock) void k_bounds(int d, Dims dd,
         }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        for (int p = 0; p < kMaxAxes; ++p) {
-            acc.mn[p] = fminf(acc.mn[p], __shfl_xor(acc.mn[p], o));
-            acc.mx[p] = fmaxf(acc.mx[p], __shfl_xor(acc.mx[p], o));
-        }
-        acc.bad |= __shfl_xor(acc.bad, o);
+    for (int p = 0; p < kMaxAxes; ++p) {
+        acc.mn[p] = wave_min(acc.mn[p]);
+        acc.mx[p] = wave_max(acc.mx[p]);
     }
+    acc.bad = wave_any(acc.bad);
     __shared__ BoundsPartial sp[kWaves];
     if (lane_id() == 0) {
         BoundsPartial &p = sp[wave_id()];
@@ -331,13 +365,11 @@ __device__ void derive_plan(const BoundsPartial *__restrict__ part, int nparts, 
         bad |= pb[u].nonfinite;
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        for (int p = 0; p < kMaxAxes; ++p) {
-            mn[p] = fminf(mn[p], __shfl_xor(mn[p], o));
-            mx[p] = fmaxf(mx[p], __shfl_xor(mx[p], o));
-        }
-        bad |= __shfl_xor(bad, o);
+    for (int p = 0; p < kMaxAxes; ++p) {
+        mn[p] = wave_min(mn[p]);
+        mx[p] = wave_max(mx[p]);
     }
+    bad = wave_any(bad);
     if (lane_id() != 0) return;
     // Cell edge r (1 + 2^-10) / cell_div.  A pair that passes the float32 test has
     // |x_p - y_p| < r exactly along every coordinate (partial sums never exceed D,
