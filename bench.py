@@ -63,6 +63,8 @@ def parse():
                     help="print a markdown summary of rocprofv3 output folders (TRACE FETCH WRITE CFETCH CWRITE "
                          "[SQ]) and exit")
     ap.add_argument("--commands", nargs="+", default=None, help="the profiling commands, for the summary")
+    ap.add_argument("--bench-line", default=None,
+                    help="stdout of the profiled bench run (its JSON line gives n, d and E for the summary)")
     ap.add_argument("--batch-only", type=int, default=0, metavar="CALLS",
                     help="build the 64-event batch CALLS times with the default binned coordinates and "
                          "default grid (a run to profile) and exit")
@@ -76,6 +78,39 @@ def search_bytes(n: int, dpad: int, n_cells: int, E: int) -> int:
     sorted rows' (original row, cell) words, cell starts, kept counts and the
     unsorted neighbour lists (4 bytes per edge)."""
     return n * dpad * 4 + 8 * n + 4 * (n_cells + 1) + 4 * n + 4 * E
+
+
+def cells_max(n: int) -> int:
+    """Cells reserved (cleared and scanned) for an event of n points."""
+    return min(max(2 * n, 1 << 15), 1 << 24)
+
+
+def kernel_bytes(kernel: str, n: int, d: int, E: int, axes: int = 4) -> int | None:
+    """Algorithmic HBM bytes of one launch of each kernel of the path on one event
+    (inputs read once, outputs written once): what the counted traffic of the
+    profile is compared with."""
+    dpad = next(p for p in (4, 8, 12, 16, 24, 32, 48, 64) if d <= p)
+    cells = cells_max(n)
+    tiles = (n + 255) // 256
+    table = {
+        # points read; histogram cleared
+        "k_bounds": 4 * n * d + 4 * cells,
+        # binned coordinates read; packed cell and rank written; one counter updated per point
+        "k_keys": 4 * axes * n + 8 * n + 8 * min(n, cells),
+        # histogram read, cell starts written
+        "k_scan_tiles<unsigned int>": 4 * cells + 4 * (cells + 1),
+        # packed cell, rank, cell start and row read; padded row, (row, cell) pair and inverse written
+        "k_scatter": 12 * n + 4 * n * d + 4 * n * dpad + 12 * n,
+        "k_search": search_bytes(n, dpad, cells, E),
+        # kept counts read, tile totals written
+        "k_kept_sums": 4 * n + 8 * tiles,
+        # kept counts and list entries read, int64 edges written
+        "k_place": 4 * n + 4 * E + 16 * E,
+    }
+    for k, v in table.items():
+        if kernel == k or kernel.startswith(k + "<"):
+            return v
+    return None
 
 
 def path_bytes(n: int, d: int, E: int) -> int:
@@ -299,10 +334,12 @@ VALU_CYCLES = 4
 
 
 def summarize(trace_dir: str, fetch_dir: str, write_dir: str, cfetch_dir: str, cwrite_dir: str,
-              commands: list[str], sq_dir: str | None = None) -> str:
+              commands: list[str], sq_dir: str | None = None, bench_line: str | None = None) -> str:
     """Markdown summary of rocprofv3 outputs: kernel durations, HBM bytes per
-    dispatch scaled by the copy calibration and, given a folder of SQ/GRBM
-    counters, VALU issue utilisation per kernel."""
+    dispatch scaled by the copy calibration (beside each kernel's algorithmic
+    bytes, from the event's n, d and E in the profiled run's own JSON line when
+    given) and, given a folder of SQ/GRBM counters, VALU issue utilisation per
+    kernel."""
     import csv
     import glob
 
@@ -339,11 +376,26 @@ def summarize(trace_dir: str, fetch_dir: str, write_dir: str, cfetch_dir: str, c
             f"calibration: `{commands[3]}`; `{commands[4]}`", "",
             f"copy kernel `{ck}` of 256 MiB reads FETCH_SIZE {cf[ck]:.0f} KiB and WRITE_SIZE {cw[ck]:.0f} KiB "
             f"per dispatch: scale factors fetch x{f_scale:.3f}, write x{w_scale:.3f}", "",
-            "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes |", "|---|---|---|---|"]
+            "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes | algorithmic bytes | counted / algorithmic |",
+            "|---|---|---|---|---|---|"]
+    ev = None
+    if bench_line:
+        with open(bench_line) as f:
+            for line in f:
+                if line.startswith("{"):
+                    ev = json.loads(line)
     ours = [k for k in fetch if k.startswith("k_")]
     for k in ours:
         b = int(round((fetch[k] * f_scale + write.get(k, 0.0) * w_scale) * 1024))
-        out.append(f"| {k} | {fetch[k]:.1f} | {write.get(k, 0.0):.1f} | {b} |")
+        alg = None
+        if ev is not None:
+            alg = kernel_bytes(k, ev["config"]["n"], ev["config"]["d"], ev["edges"], ev["config"]["axes"])
+        a_txt = f"{alg}" if alg else "—"
+        r_txt = f"{b / alg:.2f}" if alg else "—"
+        out.append(f"| {k} | {fetch[k]:.1f} | {write.get(k, 0.0):.1f} | {b} | {a_txt} | {r_txt} |")
+    if ev is not None:
+        out += ["", f"algorithmic bytes for n = {ev['config']['n']}, d = {ev['config']['d']}, "
+                    f"E = {ev['edges']}, {ev['config']['axes']} binned coordinates (the profiled run's own line)"]
     lines = []
     for k in ours:
         b = int(round((fetch[k] * f_scale + write.get(k, 0.0) * w_scale) * 1024))
@@ -619,7 +671,8 @@ def main():
             raise SystemExit("--summarize takes TRACE FETCH WRITE CFETCH CWRITE [SQ]")
         cmds = args.commands or ["?"] * len(args.summarize)
         print(summarize(*args.summarize[:5], commands=cmds,
-                        sq_dir=args.summarize[5] if len(args.summarize) == 6 else None))
+                        sq_dir=args.summarize[5] if len(args.summarize) == 6 else None,
+                        bench_line=args.bench_line))
         return
     if args.copy_probe:
         copy_probe()
