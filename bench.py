@@ -744,6 +744,13 @@ def main():
             stage_sum[k] += v
     stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
     st = stats.as_dict()
+    # Pairs the paper's three-coordinate grid examines for the same edges (one call
+    # with three binned coordinates, same cell edge): the work this search replaces.
+    st3 = frnn.FrnnStats()
+    E3 = step(dataclasses.replace(cfg, axes=3, dims=None), st3)
+    if E3 != E:
+        raise RuntimeError(f"three binned coordinates gave {E3} edges, four gave {E}")
+    pairs3 = st3.as_dict()["candidates"]
 
     dpad = next(p for p in (4, 8, 12, 16, 24, 32, 48, 64) if d <= p)
     t_search = stage_ms["search"] * 1e-3
@@ -767,6 +774,8 @@ def main():
                 "frac_of_plain_lane_peak": ops / t_search / 1e12 / PLAIN_LANE_PEAK_TOPS,
                 "executed_ops": executed, "survivors": st["survivors"],
                 "executed_frac": executed / t_search / 1e12 / FP32_PEAK_TFLOPS,
+                "three_coordinate_grid_pairs": pairs3,
+                "three_coordinate_grid_frac": pairs3 * (3 * d + 1) / t_search / 1e12 / FP32_PEAK_TFLOPS,
                 "valu_issue_util": stored_valu(kname) if args.workload == "single" else None}
     roofline_hbm = {"bound": "hbm", "achieved": sb / t_search / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": sb / t_search / 1e9 / HBM_PEAK_GBS, "bytes": sb}
