@@ -192,7 +192,7 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.sorted = cv.take<float>(static_cast<size_t>(rows + 1) * dpad);
     ws.sorted_id = cv.take<unsigned int>(2 * rows);
     ws.kept = cv.take<unsigned int>(rows);
-    ws.inv = cv.take<unsigned int>(rows);
+    ws.long_slots = cv.take<unsigned int>(rows);
     ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap);
     ws.tested = cv.take<unsigned long long>(2 * kMaxSearchBlocks);
     ws.capped_blk = cv.take<unsigned int>(kMaxSearchBlocks);

@@ -30,11 +30,12 @@ constexpr int kPlaceBlock = 256;     // threads per workgroup of the placement p
 constexpr int kPlaceTile = 256;      // queries per workgroup of the placement pass (and kept tile)
 constexpr int kKeptGroup = 64;       // kept tiles per second-level total
 constexpr int kFlatTiles = 4096;     // up to this many kept tiles, placement sums the tile totals directly
-constexpr int kOwnerWindow = 4096;   // output positions mapped to their query at a time in placement
+constexpr int kOwnerWindow = 4096;   // output positions formed in LDS at a time in placement
+constexpr int kPlaceMinBlocks = 512; // placement workgroups at least (all of them collect long lists)
 constexpr int kMaxEvents = 65535;  // events per call (the second grid dimension)
 // A kept count with this bit set belongs to a long list (more than kListCap
 // neighbours, or more than K without the search's own selection), which the
-// placement pass collects again; other lists sit at kListCap slots per sorted row.
+// placement pass collects again; other lists sit at kListCap slots per original row.
 constexpr unsigned int kKeptLong = 1u << 31;
 
 // One event of a call: its rows in the concatenated points and its share of the
@@ -115,7 +116,7 @@ struct Workspace {
     float *sorted;              // [rows, dpad] points in cell order, zero-padded rows
     unsigned int *sorted_id;    // [2 rows] per sorted row: its original row, then its packed cell
     unsigned int *kept;         // [rows] neighbours kept per original row (| kKeptLong for a long list)
-    unsigned int *inv;          // [rows] sorted row of each original row
+    unsigned int *long_slots;   // [rows] sorted rows of the queries with long lists, in queue order
     unsigned int *temp;         // [rows * kListCap] neighbour lists of up to kListCap entries
     unsigned long long *tested; // [2 kMaxSearchBlocks] pairs examined, then pairs fully tested, per search workgroup
     unsigned int *capped_blk;   // [kMaxSearchBlocks] capped queries per search workgroup

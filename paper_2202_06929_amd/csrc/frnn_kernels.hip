@@ -553,8 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
                                                     const unsigned int *__restrict__ cell_start,
                                                     const Counters *__restrict__ ctr,
                                                     float *__restrict__ sorted,
-                                                    unsigned int *__restrict__ sorted_id,
-                                                    unsigned int *__restrict__ inv) {
+                                                    unsigned int *__restrict__ sorted_id) {
     if (ctr->abort) return;
     const EventDesc E = ev[blockIdx.y];
     const Plan P = plans[blockIdx.y];
@@ -588,7 +587,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
         // The original row and the packed cell of a sorted row sit side by side, so
         // the scattered write is one 8-byte store instead of two 4-byte ones.
         reinterpret_cast<uint2 *>(sorted_id)[slot] = make_uint2(static_cast<unsigned int>(gi), pc);
-        inv[gi] = slot;
     }
 }
 
@@ -678,6 +676,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                                    const Plan *__restrict__ plans, float r2, int K,
                                                    unsigned int *__restrict__ kept,
                                                    unsigned int *__restrict__ temp,
+                                                   unsigned int *__restrict__ long_slots,
                                                    Counters *__restrict__ ctr,
                                                    unsigned long long *__restrict__ tested_out,
                                                    unsigned int *__restrict__ capped_out, int prio) {
@@ -945,8 +944,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     __shfl(static_cast<int>(v_orig), static_cast<int>((q0 - win + lane) & 63u)));
                 wave_lds_sync();
                 // Kept counts for every query; lists that fit are stored at a fixed place
-                // (kListCap slots per original row), longer ones are collected again by
-                // the placement pass.
+                // (kListCap slots per original row); the sorted rows of longer ones are
+                // queued (one atomic each) for the placement pass to collect again.
                 const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
                                   (SEL || cnt <= static_cast<unsigned int>(K));
                 if (lane < Qn) {
@@ -957,7 +956,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     const unsigned int kq = min(cnt, static_cast<unsigned int>(K));
                     kept[i] = kq | (fits ? 0u : kKeptLong);
                     if (cnt > static_cast<unsigned int>(K)) ++capped;
-                    if (!fits) atomicAdd(&ctr->heavy_count, 1u);
+                    if (!fits) long_slots[atomicAdd(&ctr->heavy_count, 1u)] = q0 + lane;
                 }
                 // Lists that fit go to their fixed place (kListCap slots per original row)
                 // as found, in 16-byte pieces; the placement pass orders every such list
@@ -1119,8 +1118,8 @@ __global__ __launch_bounds__(kBlock) void k_kept_sums(int n, const unsigned int 
 
 // --------------------------------------------------------------- long lists
 
-// LDS of the long-list collection (besides the kept ids, which go to the
-// placement pass's staging array: it holds nothing yet at that point).
+// LDS of the long-list collection (besides the hit keys and the kept ids, which
+// use the placement pass's window arrays: they hold nothing at that point).
 template <int DP>
 struct LongLds {
     unsigned int hist[256];
@@ -1128,22 +1127,31 @@ struct LongLds {
     unsigned int run_start[64];
     unsigned int run_pre[65];
     unsigned int fill;
-    unsigned int remaining;
+    unsigned int left;
     unsigned long long prefix;
 };
 
+// Hit keys a long list keeps in LDS (the two window arrays of the placement pass);
+// a list with more hits is selected by enumerating its candidates again per pass.
+constexpr unsigned int kKeyCap = kOwnerWindow;
+
 // One long list, collected again by the whole workgroup (every thread calls this
 // with the same arguments): the query's candidates are enumerated over the same
-// runs of cells as in the search; with `select` (its kept count is K, so it may
-// have more than K hits) the K first hits in (D, j) order are found by an
-// MSB-first radix select over (D bits << 32 | j) keys, D being never negative;
-// the kept ids are sorted by a bitonic network in LDS and written, local to the
-// query's event, to out[0, n_out).
+// runs of cells as in the search and its hits keyed (bits(D) << 32 | j), which
+// orders them by (D, j) since D is never negative.  With more hits than n_out
+// (the cap binds) the n_out-th smallest key is found by an MSB-first radix select
+// (8 passes of 8 bits; in each pass a scan over the 256 bin counts finds the bin
+// that holds it), over the keys in LDS or, past kKeyCap hits, by enumerating the
+// candidates again.  The kept ids are sorted by a bitonic network in LDS and
+// written, local to the query's event, to out[0, n_out).
 template <int DP>
 __device__ void long_list(const float *__restrict__ sorted, const unsigned int *__restrict__ sorted_id,
                           const unsigned int *__restrict__ cell_start, const Plan &P, unsigned int cell0,
-                          unsigned int slot, float r2, unsigned int n_out, bool select, long long row0,
-                          long long *__restrict__ out, unsigned int *__restrict__ buf, LongLds<DP> &L) {
+                          unsigned int slot, float r2, unsigned int n_out, long long row0,
+                          long long *__restrict__ out, unsigned int *__restrict__ wbuf,
+                          unsigned long long *__restrict__ scratch, LongLds<DP> &L) {
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(wbuf);  // [kKeyCap]
+    unsigned int *ids = wbuf;                                                  // [kMaxK], after the keys are read
     const int nruns = run_count(P);
     for (int k = threadIdx.x; k < DP; k += kPlaceBlock) L.qv[k] = sorted[static_cast<size_t>(slot) * DP + k];
     if (wave_id() == 0) {
@@ -1153,7 +1161,10 @@ __device__ void long_list(const float *__restrict__ sorted, const unsigned int *
         const unsigned int M = wave_runs(u, cell0, P, run_lane(P), cell_start, start, pre, end);
         L.run_start[lane_id()] = start;
         L.run_pre[lane_id()] = pre;
-        if (lane_id() == 0) L.run_pre[64] = M;
+        if (lane_id() == 0) {
+            L.run_pre[64] = M;
+            L.fill = 0u;
+        }
     }
     __syncthreads();
     const unsigned int M = L.run_pre[64];
@@ -1161,107 +1172,161 @@ __device__ void long_list(const float *__restrict__ sorted, const unsigned int *
 #pragma unroll
     for (int k = 0; k < DP; ++k) q[k] = L.qv[k];
 
+    // Candidate m lies in the last run that starts at or before it (runs are
+    // numbered in order, so their starts ascend).
     auto hit_key = [&](unsigned int m, bool &ok) -> unsigned long long {
-        int r = 0;
-        for (int t = 1; t < nruns; ++t) r += (m >= L.run_pre[t]) ? 1 : 0;
-        const unsigned int s = L.run_start[r] + (m - L.run_pre[r]);
+        int lo = 0, hi = nruns - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.run_pre[mid] <= m) lo = mid;
+            else hi = mid - 1;
+        }
+        const unsigned int s = L.run_start[lo] + (m - L.run_pre[lo]);
         float c[DP];
         load_row<DP>(sorted, s, c);
         const float D = sq_dist<DP>(c, q);
         ok = (D < r2) && (s != slot);
         return (static_cast<unsigned long long>(__float_as_uint(D)) << 32) | sorted_id[2u * s];
     };
+    // One radix pass: the bin of the left-th smallest key among those matching the
+    // prefix above `shift + 8`, and how many of them lie in lower bins.
+    auto pick_bin = [&](unsigned long long prefix, int shift) {
+        const unsigned int c = L.hist[threadIdx.x];
+        const unsigned int left = L.left;  // read before the scan's barriers; the winner writes after them
+        const unsigned int below = static_cast<unsigned int>(block_exclusive_scan(c, scratch));
+        if (below < left && left <= below + c) {
+            L.left = left - below;
+            L.prefix = prefix | (static_cast<unsigned long long>(threadIdx.x) << shift);
+        }
+        __syncthreads();
+    };
 
-    unsigned long long limit = ~0ull;  // keep hits with key <= limit
-    if (select) {
-        if (threadIdx.x == 0) {
-            L.prefix = 0ull;
-            L.remaining = n_out;
-        }
-        for (int pass = 0; pass < 8; ++pass) {
-            const int shift = 56 - 8 * pass;
-            for (int b = threadIdx.x; b < 256; b += kPlaceBlock) L.hist[b] = 0u;
-            __syncthreads();
-            const unsigned long long prefix = L.prefix;
-            for (unsigned int m = threadIdx.x; m < M; m += kPlaceBlock) {
-                bool ok;
-                const unsigned long long key = hit_key(m, ok);
-                const bool match = pass == 0 || (key >> (shift + 8)) == (prefix >> (shift + 8));
-                if (ok && match) atomicAdd(&L.hist[(key >> shift) & 255ull], 1u);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                unsigned int rem = L.remaining, b = 0;
-                while (b < 255 && L.hist[b] < rem) {
-                    rem -= L.hist[b];
-                    ++b;
-                }
-                L.remaining = rem;
-                L.prefix = prefix | (static_cast<unsigned long long>(b) << shift);
-            }
-            __syncthreads();
-        }
-        limit = L.prefix;
-    }
-    if (threadIdx.x == 0) L.fill = 0u;
-    __syncthreads();
+    // Every hit, keyed, into LDS (as many as fit).
     for (unsigned int m = threadIdx.x; m < M; m += kPlaceBlock) {
         bool ok;
         const unsigned long long key = hit_key(m, ok);
-        if (ok && key <= limit) {
+        if (ok) {
             const unsigned int pos = atomicAdd(&L.fill, 1u);
-            if (pos < static_cast<unsigned int>(kMaxK)) buf[pos] = static_cast<unsigned int>(key & 0xffffffffull);
+            if (pos < kKeyCap) keys[pos] = key;
         }
     }
     __syncthreads();
-    // Bitonic sort of buf by neighbour id; slots past the hits found hold the
-    // largest value (only a corrupted kept count could leave any of them in [0, n_out)).
+    const unsigned int h = L.fill;
+    const bool in_lds = h <= kKeyCap;
+    unsigned long long limit = ~0ull;  // keep hits with key <= limit
+    if (h > n_out) {
+        if (threadIdx.x == 0) {
+            L.prefix = 0ull;
+            L.left = n_out;
+        }
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            L.hist[threadIdx.x] = 0u;
+            __syncthreads();
+            const unsigned long long prefix = L.prefix;
+            auto count = [&](unsigned long long key) {
+                if (pass == 0 || (key >> (shift + 8)) == (prefix >> (shift + 8)))
+                    atomicAdd(&L.hist[(key >> shift) & 255ull], 1u);
+            };
+            if (in_lds) {
+                for (unsigned int k = threadIdx.x; k < h; k += kPlaceBlock) count(keys[k]);
+            } else {
+                for (unsigned int m = threadIdx.x; m < M; m += kPlaceBlock) {
+                    bool ok;
+                    const unsigned long long key = hit_key(m, ok);
+                    if (ok) count(key);
+                }
+            }
+            __syncthreads();
+            pick_bin(prefix, shift);
+        }
+        limit = L.prefix;
+    }
+    // The kept ids, compacted into LDS (keys in LDS are read into registers first,
+    // since the ids overwrite them).
+    constexpr int kPer = kKeyCap / kPlaceBlock;
+    if (in_lds) {
+        unsigned long long mine[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const unsigned int k = threadIdx.x + static_cast<unsigned int>(j) * kPlaceBlock;
+            mine[j] = k < h ? keys[k] : ~0ull;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) L.fill = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (mine[j] != ~0ull && mine[j] <= limit) {
+                const unsigned int pos = atomicAdd(&L.fill, 1u);
+                if (pos < static_cast<unsigned int>(kMaxK)) ids[pos] = static_cast<unsigned int>(mine[j]);
+            }
+        }
+    } else {
+        __syncthreads();
+        if (threadIdx.x == 0) L.fill = 0u;
+        __syncthreads();
+        for (unsigned int m = threadIdx.x; m < M; m += kPlaceBlock) {
+            bool ok;
+            const unsigned long long key = hit_key(m, ok);
+            if (ok && key <= limit) {
+                const unsigned int pos = atomicAdd(&L.fill, 1u);
+                if (pos < static_cast<unsigned int>(kMaxK)) ids[pos] = static_cast<unsigned int>(key);
+            }
+        }
+    }
+    __syncthreads();
+    // Bitonic sort of the ids by value; slots past the ids found hold the largest
+    // value (only a corrupted kept count could leave any of them in [0, n_out)).
     const unsigned int found = min(L.fill, static_cast<unsigned int>(kMaxK));
     unsigned int size = 1;
     while (size < n_out) size <<= 1;
-    for (unsigned int e = found + threadIdx.x; e < size; e += kPlaceBlock) buf[e] = 0xffffffffu;
+    for (unsigned int e = found + threadIdx.x; e < size; e += kPlaceBlock) ids[e] = 0xffffffffu;
     __syncthreads();
     for (unsigned int k = 2; k <= size; k <<= 1) {
         for (unsigned int j = k >> 1; j > 0; j >>= 1) {
             for (unsigned int e = threadIdx.x; e < size; e += kPlaceBlock) {
                 const unsigned int o = e ^ j;
                 if (o > e) {
-                    const unsigned int a = buf[e], b = buf[o];
+                    const unsigned int a = ids[e], b = ids[o];
                     const bool up = (e & k) == 0;
                     if ((a > b) == up) {
-                        buf[e] = b;
-                        buf[o] = a;
+                        ids[e] = b;
+                        ids[o] = a;
                     }
                 }
             }
             __syncthreads();
         }
     }
-    for (unsigned int t = threadIdx.x; t < n_out; t += kPlaceBlock) out[t] = static_cast<long long>(buf[t]) - row0;
+    for (unsigned int t = threadIdx.x; t < n_out; t += kPlaceBlock) out[t] = static_cast<long long>(ids[t]) - row0;
     __syncthreads();
 }
 
 // ------------------------------------------------------------------- place
 
-// Block b owns queries [kPlaceTile b, kPlaceTile (b + 1)), one per thread.  Its
-// first output position is the sum of the kept totals before it (whole groups of
-// kKeptGroup tiles, then the tiles of its own group); a block scan of its kept
-// counts gives each query's offset.  Long lists of the block's queries are
-// collected again and written first, one at a time by the whole block.  Lists in
-// the fixed kListCap-slot places come from the search in the order their hits were
-// found: each query's thread sorts its list in registers.  The block's output is
-// then formed in LDS a window at a time (each query's thread puts its row and its
+// Block b < tiles_kept owns queries [kPlaceTile b, kPlaceTile (b + 1)), one per
+// thread.  Its first output position is the sum of the kept totals before it
+// (whole groups of kKeptGroup tiles, then the tiles of its own group); a block
+// scan of its kept counts gives each query's offset.  Lists in the fixed
+// kListCap-slot places come from the search in the order their hits were found:
+// each query's thread sorts its list in registers.  The block's output is then
+// formed in LDS a window at a time (each query's thread puts its row and its
 // neighbours at its own positions), so that consecutive threads write consecutive
-// int64 positions.  Indices are made local to each query's event.  Block 0 writes
-// the report and the status; the block holding an event's first row writes its
-// edge offset.
+// int64 positions; the neighbour positions of a long list are left to its
+// collector.  Indices are made local to each query's event.  Block 0 writes the
+// report and the status; the block holding an event's first row writes its edge
+// offset.  Then every block, including those past the tiles (the grid has at least
+// kPlaceMinBlocks), collects the long lists of the search's queue in turn: the
+// list's output position is the sum of the tile totals before its query's tile and
+// of the kept counts before it in that tile.
 template <int DP>
 __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const EventDesc *__restrict__ ev,
                                                        int n_events, const unsigned int *__restrict__ kept,
                                                        const unsigned long long *__restrict__ sums_kept,
                                                        const unsigned long long *__restrict__ sums_kept2,
                                                        int groups_kept, int tiles_kept,
-                                                       const unsigned int *__restrict__ inv,
+                                                       const unsigned int *__restrict__ long_slots,
                                                        const unsigned int *__restrict__ temp,
                                                        const float *__restrict__ sorted,
                                                        const unsigned int *__restrict__ sorted_id,
@@ -1272,22 +1337,21 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                                                        long long *__restrict__ edge_off,
                                                        Report *__restrict__ report) {
     static_assert(kPlaceBlock == kPlaceTile && kPlaceTile <= 256, "one query per thread, owner ids fit a byte");
-    static_assert(kOwnerWindow >= kMaxK, "a window's array holds a long list");
-    // A window of the block's output (event-local rows and neighbours); a
-    // neighbour entry of kSkip belongs to a long list, which is in place already.
+    static_assert(kOwnerWindow >= kMaxK && kPlaceBlock == 256, "the window arrays hold a long list's keys");
+    // A window of the block's output (event-local rows, then neighbours); a
+    // neighbour entry of kSkip belongs to a long list, written by its collector.
     constexpr unsigned int kSkip = 0xffffffffu;
     __shared__ unsigned int o[kPlaceTile + 1];
-    __shared__ unsigned int wsrc[kOwnerWindow];
-    __shared__ unsigned int wdst[kOwnerWindow];
-    __shared__ unsigned char long_q[kPlaceTile];  // the block's long-list queries, in order
-    __shared__ unsigned int n_long_s;
+    __shared__ __align__(16) unsigned int wbuf[2 * kOwnerWindow];
+    unsigned int *wsrc = wbuf;
+    unsigned int *wdst = wbuf + kOwnerWindow;
     __shared__ unsigned long long scratch[kWaves];
     __shared__ LongLds<DP> L;
     const bool abort = ctr->abort != 0;
     const int b = static_cast<int>(blockIdx.x);
-    const int g = b / kKeptGroup;
+    const bool tile_block = b < tiles_kept;
     const long long i0 = static_cast<long long>(b) * kPlaceTile;
-    const int cnt = static_cast<int>(rows - i0 < kPlaceTile ? rows - i0 : kPlaceTile);
+    const int cnt = tile_block ? static_cast<int>(rows - i0 < kPlaceTile ? rows - i0 : kPlaceTile) : 0;
     const int q = threadIdx.x;
     // The query's kept count and its list of up to kListCap (at the query's own
     // fixed place) are requested first, so that their round trips overlap the sums
@@ -1309,23 +1373,30 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
             v[4 * c + 3] = w.w;
         }
     }
+    // Sum of the tile totals before tile t (and of all of them), one part per thread.
+    auto tile_prefix = [&](int t, unsigned long long &before, unsigned long long &all) {
+        before = 0;
+        all = 0;
+        if (tiles_kept <= kFlatTiles) {
+            // Few tiles: the tile totals are summed directly.
+            for (int x = threadIdx.x; x < tiles_kept; x += kPlaceBlock) {
+                const unsigned long long y = sums_kept[x];
+                all += y;
+                if (x < t) before += y;
+            }
+        } else {
+            const int gt = t / kKeptGroup;
+            for (int x = threadIdx.x; x < groups_kept; x += kPlaceBlock) {
+                const unsigned long long y = sums_kept2[x];
+                all += y;
+                if (x < gt) before += y;
+            }
+            const int x = gt * kKeptGroup + static_cast<int>(threadIdx.x);
+            if (threadIdx.x < kKeptGroup && x < t) before += sums_kept[x];
+        }
+    };
     unsigned long long pre = 0, tot = 0;
-    if (!abort && tiles_kept <= kFlatTiles) {
-        // Few tiles: the tile totals are summed directly.
-        for (int t = threadIdx.x; t < tiles_kept; t += kPlaceBlock) {
-            const unsigned long long x = sums_kept[t];
-            tot += x;
-            if (t < b) pre += x;
-        }
-    } else if (!abort) {
-        for (int t = threadIdx.x; t < groups_kept; t += kPlaceBlock) {
-            const unsigned long long x = sums_kept2[t];
-            tot += x;
-            if (t < g) pre += x;
-        }
-        const int t = g * kKeptGroup + static_cast<int>(threadIdx.x);
-        if (threadIdx.x < kKeptGroup && t < b) pre += sums_kept[t];
-    }
+    if (!abort) tile_prefix(tile_block ? b : 0, pre, tot);
     pre = block_sum(pre, scratch);
     tot = block_sum(tot, scratch);
     const long long E = static_cast<long long>(tot);
@@ -1348,105 +1419,105 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
         edge_off[n_events] = E;
         edge_off[n_events + 1] = abort ? 2 : (overflow ? 3 : 0);
     }
-    // Offsets of the queries' edges in the block (low word) and the rank of each
-    // long list among the block's (high word).
-    const unsigned long long sx =
-        block_exclusive_scan((is_long ? 1ull << 32 : 0ull) | kq, scratch);
-    const unsigned int oq = static_cast<unsigned int>(sx);
-    if (q < cnt) {
-        o[q] = oq;
-        if (is_long) long_q[sx >> 32] = static_cast<unsigned char>(q);
-    }
-    if (q == cnt - 1) {
-        o[cnt] = oq + kq;
-        n_long_s = static_cast<unsigned int>(sx >> 32) + (is_long ? 1u : 0u);
-    }
-    __syncthreads();
-    // Edge ranges of the events whose first row lies in this block (events with no
-    // rows at the very end start at E).
-    {
-        int lo = 0, hi = n_events;  // first event whose first row is >= i0
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (ev[mid].row0 < i0) lo = mid + 1;
-            else hi = mid;
+    if (tile_block) {
+        const unsigned int oq = static_cast<unsigned int>(block_exclusive_scan(static_cast<unsigned long long>(kq), scratch));
+        if (q < cnt) o[q] = oq;
+        if (q == cnt - 1) o[cnt] = oq + kq;
+        __syncthreads();
+        // Edge ranges of the events whose first row lies in this block (events with no
+        // rows at the very end start at E).
+        {
+            int lo = 0, hi = n_events;  // first event whose first row is >= i0
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ev[mid].row0 < i0) lo = mid + 1;
+                else hi = mid;
+            }
+            const bool last_tile = b == tiles_kept - 1;
+            for (int e = lo + threadIdx.x; e < n_events; e += kPlaceBlock) {
+                const long long r0 = ev[e].row0;
+                if (r0 >= i0 + cnt && !(last_tile && r0 >= rows)) break;
+                edge_off[e] = abort ? 0 : (r0 >= rows ? E : static_cast<long long>(pre + o[r0 - i0]));
+            }
         }
-        const bool last_block = b == static_cast<int>(gridDim.x) - 1;
-        for (int e = lo + threadIdx.x; e < n_events; e += kPlaceBlock) {
-            const long long r0 = ev[e].row0;
-            if (r0 >= i0 + cnt && !(last_block && r0 >= rows)) break;
-            edge_off[e] = abort ? 0 : (r0 >= rows ? E : static_cast<long long>(pre + o[r0 - i0]));
-        }
-    }
-    if (abort || overflow) return;
-    const unsigned int brow =
-        n_events == 1 || q >= cnt ? 0u : static_cast<unsigned int>(ev[find_event(ev, n_events, i0 + q)].row0);
-    const unsigned int total = o[cnt];
-    if (pre + total > cap) return;  // cannot happen when E <= cap; never write past the outputs
-    const unsigned int n_long = n_long_s;
-    for (unsigned int h = 0; h < n_long; ++h) {
-        const int ql = long_q[h];
-        const long long gi = i0 + ql;
-        const unsigned int slot = inv[gi];
-        const int e = n_events == 1 ? 0 : find_event(ev, n_events, gi);
-        const Plan P = plans[e];
-        const unsigned int nq = o[ql + 1] - o[ql];
-        if (static_cast<long long>(slot) >= rows) continue;  // only a corrupted inverse
-        long_list<DP>(sorted, sorted_id, cell_start, P, static_cast<unsigned int>(ev[e].cell0), slot, r2, nq,
-                      nq == static_cast<unsigned int>(K), ev[e].row0, dst + pre + o[ql], wdst, L);
-    }
-    // A list from a fixed place holds the query's hits in the order they were found:
-    // its thread sorts it (a bitonic network over 16 slots, the unused ones holding
-    // the largest value).
-    if (fixed) {
+        if (abort || overflow) return;
+        const unsigned int brow =
+            n_events == 1 || q >= cnt ? 0u : static_cast<unsigned int>(ev[find_event(ev, n_events, i0 + q)].row0);
+        const unsigned int total = o[cnt];
+        if (pre + total > cap) return;  // cannot happen when E <= cap; never write past the outputs
+        // A list from a fixed place holds the query's hits in the order they were
+        // found: its thread sorts it (a bitonic network over 16 slots, the unused
+        // ones holding the largest value).
+        if (fixed) {
 #pragma unroll
-        for (int u = 0; u < kListCap; ++u) v[u] = static_cast<unsigned int>(u) < kq ? v[u] : 0xffffffffu;
+            for (int u = 0; u < kListCap; ++u) v[u] = static_cast<unsigned int>(u) < kq ? v[u] : 0xffffffffu;
 #pragma unroll
-        for (int k = 2; k <= kListCap; k <<= 1) {
+            for (int k = 2; k <= kListCap; k <<= 1) {
 #pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
-                for (int u = 0; u < kListCap; ++u) {
-                    const int l = u ^ j;
-                    if (l > u) {
-                        const unsigned int lo = v[u] < v[l] ? v[u] : v[l];
-                        const unsigned int hi = v[u] < v[l] ? v[l] : v[u];
-                        const bool up = (u & k) == 0;
-                        v[u] = up ? lo : hi;
-                        v[l] = up ? hi : lo;
+                    for (int u = 0; u < kListCap; ++u) {
+                        const int l = u ^ j;
+                        if (l > u) {
+                            const unsigned int lo = v[u] < v[l] ? v[u] : v[l];
+                            const unsigned int hi = v[u] < v[l] ? v[l] : v[u];
+                            const bool up = (u & k) == 0;
+                            v[u] = up ? lo : hi;
+                            v[l] = up ? hi : lo;
+                        }
                     }
                 }
             }
         }
-    }
-    const unsigned int il = static_cast<unsigned int>(i0 + q) - brow;  // the query's event-local row
-    for (unsigned int w0 = 0; w0 < total; w0 += kOwnerWindow) {
-        const unsigned int wend = total - w0 < kOwnerWindow ? total - w0 : kOwnerWindow;
-        if (fixed) {
+        const unsigned int il = static_cast<unsigned int>(i0 + q) - brow;  // the query's event-local row
+        for (unsigned int w0 = 0; w0 < total; w0 += kOwnerWindow) {
+            const unsigned int wend = total - w0 < kOwnerWindow ? total - w0 : kOwnerWindow;
+            if (fixed) {
 #pragma unroll
-            for (int u = 0; u < kListCap; ++u) {
-                const unsigned int pw = oq + static_cast<unsigned int>(u) - w0;  // wraps when before the window
-                if (static_cast<unsigned int>(u) < kq && oq + u >= w0 && pw < wend) {
+                for (int u = 0; u < kListCap; ++u) {
+                    const unsigned int pw = oq + static_cast<unsigned int>(u) - w0;  // wraps when before the window
+                    if (static_cast<unsigned int>(u) < kq && oq + u >= w0 && pw < wend) {
+                        wsrc[pw] = il;
+                        wdst[pw] = v[u] - brow;
+                    }
+                }
+            } else if (is_long) {
+                const unsigned int a0 = oq > w0 ? oq - w0 : 0u;
+                const unsigned int a1 = oq + kq > w0 ? min(oq + kq - w0, wend) : 0u;
+                for (unsigned int pw = a0; pw < a1; ++pw) {
                     wsrc[pw] = il;
-                    wdst[pw] = v[u] - brow;
+                    wdst[pw] = kSkip;
                 }
             }
-        } else if (is_long) {
-            const unsigned int a0 = oq > w0 ? oq - w0 : 0u;
-            const unsigned int a1 = oq + kq > w0 ? min(oq + kq - w0, wend) : 0u;
-            for (unsigned int pw = a0; pw < a1; ++pw) {
-                wsrc[pw] = il;
-                wdst[pw] = kSkip;
+            __syncthreads();
+            for (unsigned int pw = threadIdx.x; pw < wend; pw += kPlaceBlock) {
+                const long long at = static_cast<long long>(pre) + w0 + pw;
+                src[at] = wsrc[pw];
+                const unsigned int dv = wdst[pw];
+                if (dv != kSkip) dst[at] = dv;
             }
+            __syncthreads();
         }
-        __syncthreads();
-        for (unsigned int pw = threadIdx.x; pw < wend; pw += kPlaceBlock) {
-            const long long at = static_cast<long long>(pre) + w0 + pw;
-            src[at] = wsrc[pw];
-            const unsigned int dv = wdst[pw];
-            if (dv != kSkip) dst[at] = dv;
-        }
-        __syncthreads();
+    }
+    if (abort || overflow) return;
+    // Long lists of the search's queue, every gridDim-th one.
+    const unsigned int n_long = ctr->heavy_count;
+    for (unsigned int h = blockIdx.x; h < n_long; h += gridDim.x) {
+        const unsigned int slot = long_slots[h];
+        const long long gi = sorted_id[2u * slot];  // the query's original row
+        const int t = static_cast<int>(gi / kPlaceTile);
+        if (gi >= rows || t >= tiles_kept) continue;  // only a corrupted queue
+        unsigned long long at = 0, all = 0;
+        tile_prefix(t, at, all);
+        const long long x = static_cast<long long>(t) * kPlaceTile + threadIdx.x;
+        if (x < gi) at += kept[x] & ~kKeptLong;
+        at = block_sum(at, scratch);
+        const unsigned int nq = kept[gi] & ~kKeptLong;
+        if (at + nq > cap) continue;  // cannot happen when E <= cap
+        const int e = n_events == 1 ? 0 : find_event(ev, n_events, gi);
+        const Plan P = plans[e];
+        long_list<DP>(sorted, sorted_id, cell_start, P, static_cast<unsigned int>(ev[e].cell0), slot, r2, nq,
+                      ev[e].row0, dst + at, wbuf, scratch, L);
     }
 }
 
@@ -1460,18 +1531,20 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     const long long nb = (static_cast<long long>(a.max_n) + kBlock - 1) / kBlock;
     const int gs = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
     hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, ws.plans,
-                       ws.pcell, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id, ws.inv);
+                       ws.pcell, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id);
     mark(4);
     const unsigned int sq_base = static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves));
     const unsigned int sq_rem = static_cast<unsigned int>(rows % (static_cast<long long>(a.search_blocks) * kWaves));
     if (a.K < kListCap)
         hipLaunchKernelGGL((k_search<DP, true>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
                            ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
-                           a.r2, a.K, ws.kept, ws.temp, ws.ctr, ws.tested, ws.capped_blk, a.search_prio);
+                           a.r2, a.K, ws.kept, ws.temp, ws.long_slots, ws.ctr, ws.tested, ws.capped_blk,
+                           a.search_prio);
     else
         hipLaunchKernelGGL((k_search<DP, false>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
                            ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
-                           a.r2, a.K, ws.kept, ws.temp, ws.ctr, ws.tested, ws.capped_blk, a.search_prio);
+                           a.r2, a.K, ws.kept, ws.temp, ws.long_slots, ws.ctr, ws.tested, ws.capped_blk,
+                           a.search_prio);
     mark(5);
     const long long kb = (static_cast<long long>(ws.tiles_kept_n) + kWaves - 1) / kWaves;
     const int kblocks = static_cast<int>(kb > 2048 ? 2048 : kb) + 1;  // and one for the search's counts
@@ -1479,9 +1552,10 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
                        ws.sums_kept, ws.sums_kept2, ws.tiles_kept_n, ws.tested, ws.capped_blk, a.search_blocks,
                        ws.ctr);
     mark(6);
-    hipLaunchKernelGGL(k_place<DP>, dim3(static_cast<unsigned int>(ws.tiles_kept_n)), dim3(kPlaceBlock), 0, a.stream,
+    const int place_blocks = ws.tiles_kept_n > kPlaceMinBlocks ? ws.tiles_kept_n : kPlaceMinBlocks;
+    hipLaunchKernelGGL(k_place<DP>, dim3(static_cast<unsigned int>(place_blocks)), dim3(kPlaceBlock), 0, a.stream,
                        rows, ws.ev, a.n_events, ws.kept, ws.sums_kept, ws.sums_kept2, ws.groups_kept_n,
-                       ws.tiles_kept_n, ws.inv, ws.temp, ws.sorted, ws.sorted_id, ws.cell_start, a.r2, a.K,
+                       ws.tiles_kept_n, ws.long_slots, ws.temp, ws.sorted, ws.sorted_id, ws.cell_start, a.r2, a.K,
                        a.src, a.dst, a.edge_capacity, ws.plans, ws.ctr, a.edge_off_out ? a.edge_off_out : ws.edge_off,
                        a.report_out ? a.report_out : ws.report);
 }

@@ -230,6 +230,27 @@ def dense_cells(d: int, seed: int = 23) -> np.ndarray:
     return X[rng.permutation(len(X))].astype(np.float32)
 
 
+def tight_clumps(sizes, d: int, r: float, seed: int, noise: int = 0) -> np.ndarray:
+    """Clumps whose points all lie within r of one another, far from each other.
+
+    Clump k has sizes[k] points drawn uniformly from a cube of half-edge
+    r / (2.5 sqrt(d)) around a centre on a lattice of spacing 4r, so every point
+    has exactly sizes[k] - 1 neighbours within r; `noise` uniform points are
+    spread far outside the clumps (a cube of edge 10^4 r).  Shuffled float32.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    half = r / (2.5 * np.sqrt(d))
+    parts = []
+    for k, m in enumerate(sizes):
+        centre = np.zeros(d)
+        centre[0] = 4.0 * r * k
+        parts.append(centre + rng.uniform(-half, half, size=(int(m), d)))
+    if noise:
+        parts.append(rng.uniform(0.0, 1e4 * r, size=(noise, d)) + np.array([-2e4 * r] + [0.0] * (d - 1)))
+    X = np.concatenate(parts) if parts else np.zeros((0, d))
+    return X[rng.permutation(len(X))].astype(np.float32)
+
+
 def dyadic_event(n: int, d: int, seed: int, step_log2: int = 6,
                  n_clusters: int = 40, sigma: float = 0.05) -> tuple[np.ndarray, np.ndarray]:
     """Clustered points snapped to multiples of 2^-step_log2 in [-1, 1].
