@@ -77,7 +77,7 @@ __host__ __device__ constexpr int cell_bits(int axes) { return axes == 4 ? 8 : 1
 // Single-address atomics serialise across the chip (about 11 ns each), so these
 // are touched only by rare events (long lists, bad input).
 struct Counters {
-    unsigned int heavy_count;      // queries whose list is long
+    unsigned int heavy_count;      // queries whose list is long (entries of the long-list queue)
     unsigned int abort;            // some event had a non-finite coordinate
     unsigned int capped;           // queries with more than K neighbours (summed after the search)
     unsigned int pad;

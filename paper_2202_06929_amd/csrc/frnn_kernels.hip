@@ -17,11 +17,12 @@
 //                 survivors, whose sums are finished 64 at a time; each list is
 //                 stored as found
 //   k_kept_sums   kept totals per placement tile and per group of tiles
-//   k_place       output offsets from the totals and a block scan; lists longer
-//                 than the search keeps, or longer than K, collected again by the
-//                 block (the K smallest by (D, j) from an MSB-first radix select);
-//                 each short list sorted by its query's thread and staged in LDS; the
-//                 edges written to their (i asc, j asc) positions with coalesced stores
+//   k_place       output offsets from the totals and a block scan; each short list
+//                 sorted by its query's thread and the block's output formed in LDS,
+//                 then written to its (i asc, j asc) positions with coalesced
+//                 stores; then the queued lists longer than the search keeps, or
+//                 longer than K, collected again, one per workgroup at a time (the K
+//                 smallest by (D, j) from an MSB-first radix select)
 //
 // Distances follow one fixed order with every product and sum rounded on its
 // own: this file is compiled with -ffp-contract=off and the pragma below.
@@ -1336,7 +1337,7 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
                                                        const Counters *__restrict__ ctr,
                                                        long long *__restrict__ edge_off,
                                                        Report *__restrict__ report) {
-    static_assert(kPlaceBlock == kPlaceTile && kPlaceTile <= 256, "one query per thread, owner ids fit a byte");
+    static_assert(kPlaceBlock == kPlaceTile, "one query per thread");
     static_assert(kOwnerWindow >= kMaxK && kPlaceBlock == 256, "the window arrays hold a long list's keys");
     // A window of the block's output (event-local rows, then neighbours); a
     // neighbour entry of kSkip belongs to a long list, written by its collector.
