@@ -301,6 +301,33 @@ def build_batch_async(points: torch.Tensor, offsets, r: float, K: int, workspace
         ctypes.c_void_p(_stream_handle(points.device)))
 
 
+class AsyncBatch:
+    """Repeated frnn_build_batch_async calls on the same points, offsets, radius, cap,
+    workspace, outputs and config, each with its own edge_offsets buffer: the fixed
+    arguments are marshalled once, on the stream current at construction.  The
+    tensors must stay alive and in place while the object is used.
+    """
+
+    def __init__(self, points: torch.Tensor, offsets, r: float, K: int, workspace: torch.Tensor,
+                 src: torch.Tensor, dst: torch.Tensor, config: Config | None = None):
+        self._off = _offsets_array(offsets)  # kept alive: the call reads it
+        self._n_events = self._off.size - 1
+        self._cfg = config.to_c() if config is not None else None
+        self._fn = lib().frnn_build_batch_async
+        self._head = (ctypes.c_void_p(points.data_ptr()), self._off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                      self._n_events, points.shape[1], ctypes.c_float(r), K, ctypes.c_void_p(workspace.data_ptr()),
+                      workspace.numel(), ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                      src.numel())
+        self._tail = (ctypes.byref(self._cfg) if self._cfg is not None else None,
+                      ctypes.c_void_p(_stream_handle(points.device)))
+
+    def __call__(self, edge_offsets: torch.Tensor) -> int:
+        """Enqueues one build; edge_offsets as for build_batch_async.  Returns its status."""
+        if edge_offsets.numel() < self._n_events + 2 or edge_offsets.dtype != torch.int64:
+            raise ValueError("edge_offsets must be a device int64 tensor of n_events + 2 entries")
+        return self._fn(*self._head, ctypes.c_void_p(edge_offsets.data_ptr()), *self._tail)
+
+
 def build_events_async(event_points: list[torch.Tensor], r: float, K: int, workspace: torch.Tensor,
                        src: torch.Tensor, dst: torch.Tensor, edge_offsets: torch.Tensor,
                        config: Config | None = None) -> int:

@@ -394,3 +394,25 @@ def test_served_stream_of_full_size_events_matches_oracle():
     got = [np.ascontiguousarray(req.edges.cpu().numpy()) for req in reqs]
     for g, w in zip(got, _oracle_many(host, 0.1, 256)):
         assert_same(g, w)
+
+
+def test_prepared_async_batch_matches_the_plain_call():
+    evs = _batch_case()
+    offsets = np.concatenate([[0], np.cumsum([len(x) for x in evs])]).astype(np.int64)
+    pts = torch.from_numpy(np.concatenate(evs)).to(DEV)
+    log(f"prepared async batch: {len(evs)} events, {offsets[-1]} rows")
+    want, eo_want = frnn.build_batch(pts, offsets, 0.1, 64)
+    cap = want.shape[1] + 64
+    ws = torch.empty(frnn.batch_workspace_bytes(offsets, 8), dtype=torch.uint8, device=DEV)
+    out = torch.full((2, cap), -7, dtype=torch.int64, device=DEV)
+    slots = torch.full((3, len(evs) + 2), -1, dtype=torch.int64, device=DEV)
+    call = frnn.AsyncBatch(pts, offsets, 0.1, 64, ws, out[0], out[1])
+    for k in range(3):
+        assert call(slots[k]) == frnn.FRNN_OK
+    torch.cuda.synchronize()
+    got = slots.cpu().numpy()
+    for k in range(3):
+        assert np.array_equal(got[k, :-1], eo_want) and got[k, -1] == 0
+    assert torch.equal(out[:, :want.shape[1]], want)
+    with pytest.raises(ValueError):
+        call(torch.zeros(1, dtype=torch.int64, device=DEV))
