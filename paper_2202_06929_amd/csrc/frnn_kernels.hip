@@ -219,6 +219,33 @@ __device__ unsigned long long block_exclusive_scan(unsigned long long v, unsigne
     return before + inc - v;
 }
 
+// Block sums of a and b and the exclusive prefix of c in thread order, with one
+// barrier: red (3 kWaves entries) belongs to this call alone, so it needs no
+// barrier after it.
+__device__ void block_sums_and_scan(unsigned long long a, unsigned long long b, unsigned long long c,
+                                    unsigned long long *red, unsigned long long &sum_a, unsigned long long &sum_b,
+                                    unsigned long long &before_c) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const unsigned long long inc = wave_inclusive_scan(c);
+    if (lane_id() == 63) {
+        red[wave_id()] = a;
+        red[kWaves + wave_id()] = b;
+        red[2 * kWaves + wave_id()] = inc;
+    }
+    __syncthreads();
+    unsigned long long sa = 0, sb = 0, pre = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        sa += red[w];
+        sb += red[kWaves + w];
+        pre += w < wave_id() ? red[2 * kWaves + w] : 0ull;
+    }
+    sum_a = sa;
+    sum_b = sb;
+    before_c = pre + inc - c;
+}
+
 // ------------------------------------------------------------------ bounds
 
 // Binned coordinates of an event, axis 0 first; -1 for an axis that is not binned.
@@ -517,7 +544,7 @@ template <typename OutT>
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__restrict__ in, long long len,
                                                        const unsigned long long *__restrict__ sums,
                                                        OutT *__restrict__ out) {
-    __shared__ unsigned long long scratch[kWaves];
+    __shared__ unsigned long long red[3 * kWaves];
     const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
     if (base > len) return;
     constexpr int kPer = kScanTile / kBlock;
@@ -530,11 +557,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__res
     }
     unsigned long long off = 0;
     for (unsigned int t = threadIdx.x; t < blockIdx.x; t += kBlock) off += sums[t];
-    off = block_sum(off, scratch);
     unsigned long long tsum = 0;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) tsum += v[j];
-    unsigned long long run = block_exclusive_scan(tsum, scratch) + off;
+    unsigned long long unused, before;
+    block_sums_and_scan(off, 0ull, tsum, red, off, unused, before);
+    unsigned long long run = before + off;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const long long idx = first + j;
@@ -1396,10 +1424,12 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
             if (threadIdx.x < kKeptGroup && x < t) before += sums_kept[x];
         }
     };
+    __shared__ unsigned long long red[3 * kWaves];
     unsigned long long pre = 0, tot = 0;
     if (!abort) tile_prefix(tile_block ? b : 0, pre, tot);
-    pre = block_sum(pre, scratch);
-    tot = block_sum(tot, scratch);
+    // The block's first output position, E, and each query's offset in the block.
+    unsigned long long oq64;
+    block_sums_and_scan(pre, tot, static_cast<unsigned long long>(kq), red, pre, tot, oq64);
     const long long E = static_cast<long long>(tot);
     const bool overflow = static_cast<unsigned long long>(E) > cap;
     if (b == 0 && threadIdx.x == 0) {
@@ -1421,7 +1451,7 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
         edge_off[n_events + 1] = abort ? 2 : (overflow ? 3 : 0);
     }
     if (tile_block) {
-        const unsigned int oq = static_cast<unsigned int>(block_exclusive_scan(static_cast<unsigned long long>(kq), scratch));
+        const unsigned int oq = static_cast<unsigned int>(oq64);
         if (q < cnt) o[q] = oq;
         if (q == cnt - 1) o[cnt] = oq + kq;
         __syncthreads();
