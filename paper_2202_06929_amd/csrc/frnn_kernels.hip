@@ -486,6 +486,7 @@ constexpr int kMaxCellTiles = ((1 << 24) + kScanTile - 1) / kScanTile + 2;
 // stores its plan; every block computes the cells of a share of the event's rows.
 __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
                                                      float r, int cell_div, const EventDesc *__restrict__ ev,
+                                                     EventDesc ev0, int ev_from_arg,
                                                      const BoundsPartial *__restrict__ part, int nparts,
                                                      Plan *__restrict__ plans, Counters *__restrict__ ctr,
                                                      unsigned int *__restrict__ pcell,
@@ -495,7 +496,7 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
     __shared__ Plan P;
     __shared__ unsigned int tile_count[kMaxCellTiles];
     const int e = blockIdx.y;
-    const EventDesc E = ev[e];
+    const EventDesc E = ev_from_arg ? ev0 : ev[e];  // one event: no load before the points'
     if (blockIdx.x != 0 && static_cast<long long>(blockIdx.x) * kKeysBlock >= E.n) return;
     // One point per thread; its binned coordinates are loaded before the plan is
     // derived so that the two latencies overlap.
@@ -576,6 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__res
 // Grid (blocks, n_events): block (b, e) copies a share of event e's rows.
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const EventDesc *__restrict__ ev,
+                                                    EventDesc ev0, int ev_from_arg,
                                                     const Plan *__restrict__ plans,
                                                     const unsigned int *__restrict__ pcell,
                                                     const unsigned int *__restrict__ rank,
@@ -583,15 +585,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
                                                     const Counters *__restrict__ ctr,
                                                     float *__restrict__ sorted,
                                                     unsigned int *__restrict__ sorted_id) {
-    if (ctr->abort) return;
-    const EventDesc E = ev[blockIdx.y];
+    // The point's packed cell, rank and row are requested before the abort flag is
+    // known (they are in bounds whatever it says); the cell start, whose index needs
+    // a valid plan, only when it is clear.
+    const bool abort = ctr->abort != 0;
+    const EventDesc E = ev_from_arg ? ev0 : ev[blockIdx.y];
     const Plan P = plans[blockIdx.y];
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < E.n; i += gridDim.x * kBlock) {
         const long long gi = E.row0 + i;
         const unsigned int pc = pcell[gi];
-        int u[kMaxAxes];
-        unpack_cell(pc, P.axes, u);
-        const unsigned int slot = cell_start[static_cast<unsigned int>(E.cell0) + cell_key(u, P)] + rank[gi];
+        const unsigned int rk = rank[gi];
         float row[DP];
         if (vec4) {
             const float4 *src = reinterpret_cast<const float4 *>(E.pts + static_cast<size_t>(i) * d);
@@ -609,6 +612,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int d, int vec4, const Event
 #pragma unroll
             for (int k = 0; k < DP; ++k) row[k] = k < d ? src[k] : 0.0f;
         }
+        if (abort) return;
+        int u[kMaxAxes];
+        unpack_cell(pc, P.axes, u);
+        const unsigned int slot = cell_start[static_cast<unsigned int>(E.cell0) + cell_key(u, P)] + rk;
         float4 *out = reinterpret_cast<float4 *>(sorted + static_cast<size_t>(slot) * DP);
 #pragma unroll
         for (int k = 0; k < DP / 4; ++k)
@@ -1561,7 +1568,8 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     const long long rows = ws.rows;
     const long long nb = (static_cast<long long>(a.max_n) + kBlock - 1) / kBlock;
     const int gs = static_cast<int>(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
-    hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, ws.plans,
+    hipLaunchKernelGGL(k_scatter<DP>, dim3(gs, a.n_events), dim3(kBlock), 0, a.stream, a.d, vec4, ws.ev, a.ev0,
+                       a.ev_from_arg, ws.plans,
                        ws.pcell, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id);
     mark(4);
     const unsigned int sq_base = static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves));
@@ -1635,7 +1643,7 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
                        ws.tiles_cells_n, ws.sums_kept2, ws.groups_kept_n, ws.ctr);
     mark(1);
     hipLaunchKernelGGL(k_keys, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.d, dd, a.axes, a.r,
-                       a.cell_div, ws.ev, ws.part, a.bounds_blocks, ws.plans, ws.ctr, ws.pcell, ws.rank,
+                       a.cell_div, ws.ev, a.ev0, a.ev_from_arg, ws.part, a.bounds_blocks, ws.plans, ws.ctr, ws.pcell, ws.rank,
                        ws.cell_count, ws.sums_cells);
     mark(2);
     hipLaunchKernelGGL(k_scan_tiles<unsigned int>, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream,
