@@ -1542,9 +1542,10 @@ __global__ __launch_bounds__(kPlaceBlock) void k_place(long long rows, const Eve
     const unsigned int n_long = ctr->heavy_count;
     for (unsigned int h = blockIdx.x; h < n_long; h += gridDim.x) {
         const unsigned int slot = long_slots[h];
+        if (static_cast<long long>(slot) >= rows) continue;  // only a corrupted queue
         const long long gi = sorted_id[2u * slot];  // the query's original row
         const int t = static_cast<int>(gi / kPlaceTile);
-        if (gi >= rows || t >= tiles_kept) continue;  // only a corrupted queue
+        if (gi >= rows || t >= tiles_kept) continue;  // likewise
         unsigned long long at = 0, all = 0;
         tile_prefix(t, at, all);
         const long long x = static_cast<long long>(t) * kPlaceTile + threadIdx.x;
