@@ -107,6 +107,13 @@ def kernel_bytes(kernel: str, n: int, d: int, E: int, axes: int = 4) -> int | No
         "k_kept_sums": 4 * n + 8 * tiles,
         # kept counts and list entries read, int64 edges written
         "k_place": 4 * n + 4 * E + 16 * E,
+        # labeling of the event's graph (n vertices, E edges): parents initialised;
+        # edges read and one parent per source updated; edges read again with the
+        # parents of their ends; parents read and int64 labels written
+        "k_cc_init": 4 * n,
+        "k_cc_minhook": 16 * E + 8 * n,
+        "k_cc_hook": 16 * E + 8 * n,
+        "k_cc_label": 4 * n + 8 * n,
     }
     for k, v in table.items():
         if kernel == k or kernel.startswith(k + "<"):
