@@ -721,7 +721,6 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     constexpr int kQT = SEL ? 16 : kQTile;
     __shared__ __align__(16) unsigned int lst_all[kWaves][kQT * kListCap];
     __shared__ unsigned int lstd_all[SEL ? kWaves : 1][SEL ? kQT * kListCap : 1];  // D bits of each hit
-    __shared__ unsigned long long thr_all[SEL ? kWaves : 1][SEL ? kQT : 1];       // K-th smallest (D, j) key
     __shared__ unsigned int qorig_all[SEL ? kWaves : 1][SEL ? kQT : 1];           // original row of each query
     __shared__ unsigned int pre_all[kWaves][kQT + 1];
     __shared__ unsigned int cnt_all[kWaves][kQT];
@@ -737,7 +736,6 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     if (ctr->abort) return;
     unsigned int *lst = lst_all[wave_id()];
     unsigned int *lstd = lstd_all[SEL ? wave_id() : 0];
-    unsigned long long *thr = thr_all[SEL ? wave_id() : 0];
     unsigned int *qorig = qorig_all[SEL ? wave_id() : 0];
     unsigned int capped = 0;
     unsigned int *tpre = pre_all[wave_id()];
@@ -998,10 +996,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                 // as found, in 16-byte pieces; the placement pass orders every such list
                 // by neighbour id.  With the cap binding (SEL and more than K hits), the
                 // entries of those lists are numbered through a prefix over their
-                // lengths; a first pass finds each list's K-th smallest (D, j) key (D >= 0,
-                // so its bits order like the value) and each lane then takes one entry,
-                // finds its query by binary search and, if the entry is among the K
-                // nearest, writes it at its rank by neighbour id among them.
+                // lengths; each lane takes one entry, finds its query by binary search,
+                // ranks it by its (D, j) key within its list (D >= 0, so its bits order
+                // like the value; keys are distinct) and, if the rank is below K, writes
+                // it at that rank: the list's first K slots then hold its K nearest.
                 const unsigned int Ku = static_cast<unsigned int>(K);
                 if (fits && !(SEL && cnt > Ku)) {
                     const uint4 *from = reinterpret_cast<const uint4 *>(lst + lane * kListCap);
@@ -1036,30 +1034,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                             const unsigned int *ld = lstd + lo * kListCap;
                             const unsigned int x = t - tpre[lo];
                             const unsigned long long key = (static_cast<unsigned long long>(ld[x]) << 32) | l[x];
-                            unsigned int sr = 0;
+                            unsigned int sr = 0;  // the entry's rank by (D, j) in its list
                             for (unsigned int u = 0; u < cq; ++u)
                                 sr += ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) < key ? 1u : 0u;
-                            if (sr == Ku - 1u) thr[lo] = key;
-                        }
-                    }
-                    wave_lds_sync();
-                    for (unsigned int t0 = 0; t0 < T; t0 += 64) {
-                        const unsigned int t = t0 + lane;
-                        if (t < T) {
-                            const int lo = entry_query(t);
-                            const unsigned int cq = tcnt[lo];
-                            const unsigned int *l = lst + lo * kListCap;
-                            const unsigned int *ld = lstd + lo * kListCap;
-                            const unsigned int x = t - tpre[lo];
-                            const unsigned int j = l[x];
-                            const unsigned long long lim = thr[lo];
-                            if (((static_cast<unsigned long long>(ld[x]) << 32) | j) <= lim) {
-                                unsigned int rk = 0;
-                                for (unsigned int u = 0; u < cq; ++u)
-                                    rk += (l[u] < j && ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) <= lim)
-                                              ? 1u : 0u;
-                                temp[static_cast<size_t>(qorig[lo]) * kListCap + rk] = j;
-                            }
+                            if (sr < Ku) temp[static_cast<size_t>(qorig[lo]) * kListCap + sr] = l[x];
                         }
                     }
                 }
