@@ -3,7 +3,8 @@
 The paper defines the graph as all pairs of points closer than a constant radius
 in the embedding space (Section 2) and builds it with a grid-cell search
 (Section 3.4).  It prints no worked example, so the oracle is pinned by:
-  * the O(n^2) definition (brute force) on tiny and stress inputs;
+  * the O(n^2) definition (brute force) on tiny and stress inputs, and written
+    out in numpy float32 for sampled queries of the full-size benchmark events;
   * exact-arithmetic inputs checked against scipy's k-d tree and against
     integer squared distances (nearest-K reduction, the Section 3.1 reading);
   * float64 distances away from the radius;
@@ -52,6 +53,45 @@ def as_set(edges):
 
 
 # ---------------------------------------------------------------- brute force
+
+def _sampled_definition(X, r, K, queries):
+    """N(i) of the definition for the given queries against every point, written
+    out with numpy float32 arithmetic: differences, squares and the sum over the
+    coordinates in ascending order, each rounded to float32 (numpy fuses nothing),
+    the strict test against fl32(r * r), then the cap by (D, j)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    r32 = np.float32(r)
+    r2 = np.float32(r32 * r32)
+    out = {}
+    for i in queries:
+        t = X - X[i]
+        acc = t[:, 0] * t[:, 0]
+        for k in range(1, X.shape[1]):
+            acc = acc + t[:, k] * t[:, k]
+        hit = np.flatnonzero(acc < r2)
+        hit = hit[hit != i]
+        order = np.lexsort((hit, acc[hit]))  # by D, then j
+        out[i] = np.sort(hit[order][:K])
+    return out
+
+
+@pytest.mark.parametrize("spec", [events.SINGLE, events.HIGH], ids=["single_120k", "high_300k_12d"])
+def test_grid_matches_the_definition_on_sampled_queries_at_full_size(spec):
+    # The benchmark events themselves: 300 queries drawn at random, each against
+    # every point of the event.
+    X, _ = events.generate(spec)
+    g = oracle.frnn_grid(X, spec.r, spec.K)
+    rng = np.random.Generator(np.random.PCG64(31))
+    queries = rng.choice(len(X), size=300, replace=False)
+    want = _sampled_definition(X, spec.r, spec.K, queries)
+    starts = np.searchsorted(g[0], np.arange(len(X) + 1))
+    n_hits = 0
+    for i in queries:
+        got = g[1, starts[i]:starts[i + 1]]
+        assert np.array_equal(got, want[i]), i
+        n_hits += len(got)
+    assert n_hits > 300  # the sample holds real neighbour lists
+
 
 def test_grid_equals_brute_tiny_event():
     X, _ = events.generate(events.TINY)
