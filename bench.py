@@ -227,6 +227,28 @@ def stored_traffic(kernel: str) -> int | None:
     return value if digest == kernel_source_digest() else None
 
 
+def stored_duration_us(kernel: str) -> float | None:
+    """Average duration of `kernel` in the committed kernel-trace summary (rocprofv3),
+    or None when it is missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    digest = None
+    value = None
+    for line in text.splitlines():
+        if line.startswith("kernel sources sha256/16:"):
+            digest = line.split(":", 1)[1].strip()
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if value is None and len(cells) == 5 and cells[0] == kernel:
+            try:
+                value = float(cells[2])
+            except ValueError:
+                pass
+    return value if digest == kernel_source_digest() else None
+
+
 def stored_valu(kernel: str) -> float | None:
     """VALU issue utilisation of `kernel` from the committed counter summary, or
     None when it is missing or was taken from other kernel sources."""
@@ -782,6 +804,9 @@ def main():
     lead = 2 if dpad <= 8 else (4 if dpad == 12 else 3)
     executed = st["candidates"] * (3 * lead + 1) + st["survivors"] * (3 * (dpad - lead) + 1)
     kname = f"k_search<{dpad}, {'true' if spec.K < 16 else 'false'}>"
+    # The same kernel's average under rocprofv3 (committed summary of the default
+    # run, same sources): HIP events around a kernel also count its dispatch.
+    prof_us = stored_duration_us(kname) if args.workload == "single" else None
     roofline = {"bound": "alu", "achieved": ops / t_search / 1e12, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ops / t_search / 1e12 / FP32_PEAK_TFLOPS,
                 "traffic": stored_traffic(kname) if args.workload == "single" else None, "kernel": kname, "kernel_us": t_search * 1e6,
@@ -792,6 +817,8 @@ def main():
                 "frac_of_plain_lane_peak": ops / t_search / 1e12 / PLAIN_LANE_PEAK_TOPS,
                 "executed_ops": executed, "survivors": st["survivors"],
                 "executed_frac": executed / t_search / 1e12 / FP32_PEAK_TFLOPS,
+                "kernel_us_profile": prof_us,
+                "frac_profile": ops / (prof_us * 1e-6) / 1e12 / FP32_PEAK_TFLOPS if prof_us else None,
                 "three_coordinate_grid_pairs": pairs3,
                 "three_coordinate_grid_frac": pairs3 * (3 * d + 1) / t_search / 1e12 / FP32_PEAK_TFLOPS,
                 "valu_issue_util": stored_valu(kname) if args.workload == "single" else None}
