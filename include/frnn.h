@@ -110,8 +110,8 @@ typedef struct frnn_stats {
     int32_t dims[4];            /* binned coordinates (-1 past `axes`) */
     float cell[4];              /* cell edge per binned axis (infinite past `axes`) */
     int32_t capped_queries;     /* queries with |N(i)| > K */
-    int32_t overflow_queries;   /* queries whose list the placement pass collects again (more
-                                   than 16 neighbours, or more than K when K >= 16) */
+    int32_t overflow_queries;   /* queries with more than 16 neighbours, whose lists the
+                                   placement pass collects again */
     float stage_ms[FRNN_STAGES]; /* per-stage device time with FRNN_FLAG_TIMING, else 0 */
     int64_t survivors;          /* examined pairs whose leading partial sum stayed below r2, so
                                    that the search added the remaining terms of the distance */
