@@ -64,6 +64,8 @@ def parse():
                     help="print a markdown summary of rocprofv3 output folders (TRACE FETCH WRITE CFETCH CWRITE "
                          "[SQ]) and exit")
     ap.add_argument("--commands", nargs="+", default=None, help="the profiling commands, for the summary")
+    ap.add_argument("--lds", nargs=2, default=None, metavar=("DIR", "COMMAND"),
+                    help="rocprofv3 folder and command of an LdsBankConflict / MeanOccupancyPerCU pass")
     ap.add_argument("--bench-line", default=None,
                     help="stdout of the profiled bench run (its JSON line gives n, d and E for the summary)")
     ap.add_argument("--batch-only", type=int, default=0, metavar="CALLS",
@@ -98,8 +100,9 @@ def kernel_bytes(kernel: str, n: int, d: int, E: int, axes: int = 4) -> int | No
         "k_bounds": 4 * n * d + 4 * cells,
         # binned coordinates read; packed cell and rank written; one counter updated per point
         "k_keys": 4 * axes * n + 8 * n + 8 * min(n, cells),
-        # histogram read, cell starts written
-        "k_scan_tiles<unsigned int>": 4 * cells + 4 * (cells + 1),
+        # histogram read, cell starts written (the search's wave starts, 4 bytes a
+        # wave, are under 2% of this and not counted)
+        "k_scan_cells": 4 * cells + 4 * (cells + 1),
         # packed cell, rank, cell start and row read; padded row, (row, cell) pair and inverse written
         "k_scatter": 12 * n + 4 * n * d + 4 * n * dpad + 12 * n,
         "k_search": search_bytes(n, dpad, cells, E),
@@ -364,7 +367,8 @@ VALU_CYCLES = 4
 
 
 def summarize(trace_dir: str, fetch_dir: str, write_dir: str, cfetch_dir: str, cwrite_dir: str,
-              commands: list[str], sq_dir: str | None = None, bench_line: str | None = None) -> str:
+              commands: list[str], sq_dir: str | None = None, bench_line: str | None = None,
+              lds_dir: str | None = None, lds_command: str | None = None) -> str:
     """Markdown summary of rocprofv3 outputs: kernel durations, HBM bytes per
     dispatch scaled by the copy calibration (beside each kernel's algorithmic
     bytes, from the event's n, d and E in the profiled run's own JSON line when
@@ -451,6 +455,18 @@ def summarize(trace_dir: str, fetch_dir: str, write_dir: str, cfetch_dir: str, c
                        f"{sq['SQ_INSTS_SMEM'].get(k, 0):.0f} | {util:.3f} |")
             vlines.append(f"valu {k} issue utilisation: {util:.4f}")
         out += [""] + vlines + [""]
+    if lds_dir is not None:
+        conf, occ = counters(lds_dir, "LdsBankConflict"), counters(lds_dir, "MeanOccupancyPerCU")
+        out += ["## LDS bank conflicts and occupancy", "", f"command: `{lds_command or '?'}`", "",
+                "LdsBankConflict: bank-conflict cycles per LDS access cycle (SQ_LDS_BANK_CONFLICT over "
+                "SQ_LDS_IDX_ACTIVE less the conflicts); MeanOccupancyPerCU: resident waves per CU averaged over "
+                "the kernel's time", "", "| kernel | LDS bank conflicts per access | mean waves per CU |", "|---|---|---|"]
+        for k in ours:
+            if k in conf or k in occ:
+                c = f"{conf[k]:.3f}" if k in conf else "—"
+                o = f"{occ[k]:.1f}" if k in occ else "—"
+                out.append(f"| {k} | {c} | {o} |")
+        out.append("")
     out += [""] + lines + [""]
     return "\n".join(out)
 
@@ -702,7 +718,8 @@ def main():
         cmds = args.commands or ["?"] * len(args.summarize)
         print(summarize(*args.summarize[:5], commands=cmds,
                         sq_dir=args.summarize[5] if len(args.summarize) == 6 else None,
-                        bench_line=args.bench_line))
+                        bench_line=args.bench_line, lds_dir=args.lds[0] if args.lds else None,
+                        lds_command=args.lds[1] if args.lds else None))
         return
     if args.copy_probe:
         copy_probe()
@@ -850,6 +867,7 @@ def main():
     }
     result["identity"] = identity()
     result["copy_bandwidth"] = copy_bandwidth()
+    result["path_hbm_frac_of_copy"] = result["path_hbm_gbs"] / result["copy_bandwidth"]["gbs"]
     if args.workload == "single" and not args.no_labeling:
         result["labeling"] = labeling_bench(spec, X, pts, args.steps, args.warmup, log, not args.no_cpu_baseline)
     if not args.no_batched:

@@ -25,6 +25,9 @@ constexpr int kGridAxisMax3 = 1024;
 constexpr int kGridAxisMax4 = 256;
 constexpr int kMaxK = 4096;
 constexpr int kMaxSearchBlocks = 8192;
+// A cell's fixed cost in the search (its runs' bounds, its candidates' first
+// loads), in queries, when the queries are divided among the waves by work.
+constexpr unsigned int kTileWeight = 4;
 constexpr int kKeysBlock = 1024;     // threads per workgroup of the key/histogram pass
 constexpr int kPlaceBlock = 256;     // threads per workgroup of the placement pass
 constexpr int kPlaceTile = 256;      // queries per workgroup of the placement pass (and kept tile)
@@ -120,6 +123,7 @@ struct Workspace {
     unsigned int *temp;         // [rows * kListCap] neighbour lists of up to kListCap entries
     unsigned long long *tested; // [2 kMaxSearchBlocks] pairs examined, then pairs fully tested, per search workgroup
     unsigned int *capped_blk;   // [kMaxSearchBlocks] capped queries per search workgroup
+    unsigned int *wave_start;   // [kMaxSearchBlocks kWaves + 1] first sorted row of each search wave's share
     long long rows;
     long long cells;
     int tiles_cells_n;

@@ -6,9 +6,10 @@
 //                 all coordinates; clears the histogram, tile totals, counters
 //   k_keys        grid plan (cell edge, cells per axis), cell key of every point,
 //                 histogram with in-cell arrival rank, per-tile histogram totals
-//   k_scan_tiles  exclusive scan of the histogram -> first sorted row of each cell
+//   k_scan_cells  exclusive scan of the histogram -> first sorted row of each cell;
+//                 the search's shares of equal work (cells' fixed costs plus queries)
 //   k_scatter     counting-sort scatter: rows copied into cell order
-//   k_search      each wave takes an equal share of the queries in cell order: a
+//   k_search      each wave takes a share of equal work in cell order: a
 //                 cell's queries against the (2R+1)^(axes-1) contiguous runs of
 //                 neighbouring cells along axis 0; each lane holds one candidate (its
 //                 leading coordinates, or its whole row for rows wider than 8
@@ -494,7 +495,8 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
                                                      unsigned int *__restrict__ cell_count,
                                                      unsigned long long *__restrict__ sums_cells) {
     __shared__ Plan P;
-    __shared__ unsigned int tile_count[kMaxCellTiles];
+    // Per scan tile: points (low word) and newly occupied cells (high word).
+    __shared__ unsigned long long tile_count[kMaxCellTiles];
     const int e = blockIdx.y;
     const EventDesc E = ev_from_arg ? ev0 : ev[e];  // one event: no load before the points'
     if (blockIdx.x != 0 && static_cast<long long>(blockIdx.x) * kKeysBlock >= E.n) return;
@@ -513,7 +515,7 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
         derive_plan(part + static_cast<size_t>(e) * nparts, nparts, r, cell_div, axes, E.cells_max, &P);
     const int tile_end = static_cast<int>((E.cell0 + E.cells_max - 1) / kScanTile);
     const int ntiles = tile_end - E.tile0 + 1;
-    for (int t = threadIdx.x; t < ntiles; t += kKeysBlock) tile_count[t] = 0u;
+    for (int t = threadIdx.x; t < ntiles; t += kKeysBlock) tile_count[t] = 0ull;
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         plans[e] = P;
@@ -527,25 +529,37 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
         for (int p = 0; p < kMaxAxes; ++p) u[p] = cell_coord(x[p], P.lo[p], P.inv_c[p], P.G[p]);
         const unsigned int k = static_cast<unsigned int>(E.cell0) + cell_key(u, P);
         pcell[gi] = pack_cell(u, axes);
-        rank[gi] = atomicAdd(&cell_count[k], 1u);
-        atomicAdd(&tile_count[k / kScanTile - E.tile0], 1u);
+        const unsigned int rk = atomicAdd(&cell_count[k], 1u);
+        rank[gi] = rk;
+        // The first point of a cell (rank 0) also counts the cell as occupied.
+        atomicAdd(&tile_count[k / kScanTile - E.tile0], rk == 0u ? (1ull << 32) | 1ull : 1ull);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ntiles; t += kKeysBlock)
-        if (tile_count[t]) atomicAdd(&sums_cells[E.tile0 + t], static_cast<unsigned long long>(tile_count[t]));
+        if (tile_count[t]) atomicAdd(&sums_cells[E.tile0 + t], tile_count[t]);
 }
 
 // ------------------------------------------------------------------- scans
 
-// out[i] = sum of in[0..i) for i in [0, len]; out[len] is the total.  sums[t] holds
-// the total of tile t (kScanTile elements).  The tile's elements are requested
-// before the totals of the tiles before it are summed, so that the two round
-// trips overlap.
-template <typename OutT>
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__restrict__ in, long long len,
-                                                       const unsigned long long *__restrict__ sums,
-                                                       OutT *__restrict__ out) {
-    __shared__ unsigned long long red[3 * kWaves];
+// cell_start[c] = points in cells [0, c) for c in [0, cells]; sums[t] holds tile
+// t's points (low word) and occupied cells (high word).  The tile's counts are
+// requested before the totals of the tiles before it are summed, so that the two
+// round trips overlap.
+//
+// The same pass divides the queries among the search's n_waves waves by work
+// rather than by count: a cell weighs its points plus kTileWeight if it has any
+// (a tile's fixed cost, in queries), the cells in order span weights [0, W), and
+// wave k starts at weight floor(k W / n_waves), which falls in one cell; the wave
+// starts there at the query that many weight units past the cell's fixed cost
+// (at its first query if it falls within the cost), so a dense cell can still be
+// split among waves.  wave_start[k] is that sorted row; wave_start[n_waves] =
+// rows.
+__global__ __launch_bounds__(kBlock) void k_scan_cells(const unsigned int *__restrict__ in, long long len,
+                                                       const unsigned long long *__restrict__ sums, int tiles,
+                                                       unsigned int *__restrict__ out,
+                                                       unsigned int *__restrict__ wave_start, int n_waves,
+                                                       long long rows) {
+    __shared__ unsigned long long red[4 * kWaves];
     const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
     if (base > len) return;
     constexpr int kPer = kScanTile / kBlock;
@@ -556,19 +570,78 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const unsigned int *__res
         const long long idx = first + j;
         v[j] = idx < len ? in[idx] : 0u;
     }
-    unsigned long long off = 0;
-    for (unsigned int t = threadIdx.x; t < blockIdx.x; t += kBlock) off += sums[t];
-    unsigned long long tsum = 0;
+    // Points and weight of the tiles before this one, and the weight of them all.
+    unsigned long long c_before = 0, w_before = 0, w_all = 0;
+    for (int t = threadIdx.x; t < tiles; t += kBlock) {
+        const unsigned long long x = sums[t];
+        const unsigned long long w = (x & 0xffffffffull) + kTileWeight * (x >> 32);
+        w_all += w;
+        if (t < static_cast<int>(blockIdx.x)) {
+            c_before += x & 0xffffffffull;
+            w_before += w;
+        }
+    }
+    // This thread's points (low word) and weight (high word); a block's totals of
+    // either stay below 2^32, so the packed scan carries nothing between them.
+    unsigned long long mine = 0;
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) tsum += v[j];
-    unsigned long long unused, before;
-    block_sums_and_scan(off, 0ull, tsum, red, off, unused, before);
-    unsigned long long run = before + off;
+    for (int j = 0; j < kPer; ++j)
+        mine += (static_cast<unsigned long long>(v[j] + (v[j] ? kTileWeight : 0u)) << 32) | v[j];
+    c_before = wave_sum(c_before);
+    w_before = wave_sum(w_before);
+    w_all = wave_sum(w_all);
+    const unsigned long long inc = wave_inclusive_scan(mine);
+    if (lane_id() == 63) {
+        red[wave_id()] = c_before;
+        red[kWaves + wave_id()] = w_before;
+        red[2 * kWaves + wave_id()] = w_all;
+        red[3 * kWaves + wave_id()] = inc;
+    }
+    __syncthreads();
+    unsigned long long cb = 0, wb = 0, W = 0, pre = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        cb += red[w];
+        wb += red[kWaves + w];
+        W += red[2 * kWaves + w];
+        pre += w < wave_id() ? red[3 * kWaves + w] : 0ull;
+    }
+    pre += inc - mine;
+    unsigned long long run_c = cb + (pre & 0xffffffffull), run_w = wb + (pre >> 32);
+    const unsigned long long nw = static_cast<unsigned long long>(n_waves);
+    // Wave k starts at weight B_k = floor(k W / nw) = k q + floor(k m / nw): walk
+    // the waves whose starts fall in this thread's cells, stepping B_k without
+    // dividing.
+    const unsigned long long q = W ? W / nw : 0ull, m = W ? W % nw : 0ull;
+    unsigned long long k = W ? (run_w * nw + W - 1) / W : nw;  // the first B_k >= run_w
+    if (k == 0) k = 1;                                         // wave 0 starts at row 0
+    unsigned long long B = k * q + (k * m) / nw, frac = (k * m) % nw;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const long long idx = first + j;
-        if (idx <= len) out[idx] = static_cast<OutT>(run);
-        run += v[j];
+        if (idx <= len) out[idx] = static_cast<unsigned int>(run_c);
+        const unsigned long long w = v[j] + (v[j] ? kTileWeight : 0u);
+        for (; k < nw && B < run_w + w; ++k) {
+            // B lies in this cell: past its fixed cost, one weight unit per query.
+            const unsigned long long past = B - run_w;
+            wave_start[k] = static_cast<unsigned int>(run_c + (past > kTileWeight ? past - kTileWeight : 0ull));
+            B += q;
+            frac += m;
+            if (frac >= nw) {
+                frac -= nw;
+                ++B;
+            }
+        }
+        run_c += v[j];
+        run_w += w;
+    }
+    if (blockIdx.x == 0) {
+        if (W == 0) {  // no rows: every share is empty
+            for (int k = threadIdx.x; k <= n_waves; k += kBlock) wave_start[k] = 0u;
+        } else if (threadIdx.x == 0) {
+            wave_start[0] = 0u;
+            wave_start[n_waves] = static_cast<unsigned int>(rows);
+        }
     }
 }
 
@@ -705,8 +778,7 @@ constexpr int kSearchWaves = DP <= 8 ? 8 : (DP <= 12 ? 6 : 1);
 template <int DP, bool SEL>
 __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float *__restrict__ sorted,
                                                    const unsigned int *__restrict__ sorted_id,
-                                                   unsigned int q_base,
-                                                   unsigned int q_rem,
+                                                   const unsigned int *__restrict__ wave_start,
                                                    const EventDesc *__restrict__ ev, int n_events,
                                                    const unsigned int *__restrict__ cell_start,
                                                    const Plan *__restrict__ plans, float r2, int K,
@@ -764,18 +836,17 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
 
     // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
     // workgroups of one XCD take consecutive queries and share their rows in its L2.
-    // Each wave takes an equal, contiguous share of the queries in cell order (a
-    // share may start or end inside a cell), so a dense cell is split across
-    // waves instead of holding up one wave.
+    // Each wave takes a contiguous share of the queries in cell order of equal work
+    // (its cells' fixed costs plus its queries, divided by the cell scan; a share
+    // may start or end inside a cell, so a dense cell is split across waves instead
+    // of holding up one wave).
     const unsigned int nb = gridDim.x;
     const unsigned int xcd = blockIdx.x % 8u, per = nb / 8u, rest = nb % 8u;
     const unsigned int lb = xcd < rest ? xcd * (per + 1u) + blockIdx.x / 8u
                                        : rest * (per + 1u) + (xcd - rest) * per + blockIdx.x / 8u;
     const unsigned int gw = lb * kWaves + wave_id();
-    // Shares of n / total_waves queries, the first n % total_waves waves one more
-    // (q_base and q_rem come from the host, so no division runs here).
-    const unsigned int q_lo = gw * q_base + min(gw, q_rem);
-    const unsigned int q_hi = q_lo + q_base + (gw < q_rem ? 1u : 0u);
+    const unsigned int q_lo = wave_start[gw];
+    const unsigned int q_hi = wave_start[gw + 1u];
     Plan P;
     RunLane rl;
     unsigned int cell0 = 0;
@@ -1551,16 +1622,14 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
                        a.ev_from_arg, ws.plans,
                        ws.pcell, ws.rank, ws.cell_start, ws.ctr, ws.sorted, ws.sorted_id);
     mark(4);
-    const unsigned int sq_base = static_cast<unsigned int>(rows / (static_cast<long long>(a.search_blocks) * kWaves));
-    const unsigned int sq_rem = static_cast<unsigned int>(rows % (static_cast<long long>(a.search_blocks) * kWaves));
     if (a.K < kListCap)
         hipLaunchKernelGGL((k_search<DP, true>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
-                           ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
+                           ws.sorted_id, ws.wave_start, ws.ev, a.n_events, ws.cell_start, ws.plans,
                            a.r2, a.K, ws.kept, ws.temp, ws.long_slots, ws.ctr, ws.tested, ws.capped_blk,
                            a.search_prio);
     else
         hipLaunchKernelGGL((k_search<DP, false>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
-                           ws.sorted_id, sq_base, sq_rem, ws.ev, a.n_events, ws.cell_start, ws.plans,
+                           ws.sorted_id, ws.wave_start, ws.ev, a.n_events, ws.cell_start, ws.plans,
                            a.r2, a.K, ws.kept, ws.temp, ws.long_slots, ws.ctr, ws.tested, ws.capped_blk,
                            a.search_prio);
     mark(5);
@@ -1625,8 +1694,9 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
                        a.cell_div, ws.ev, a.ev0, a.ev_from_arg, ws.part, a.bounds_blocks, ws.plans, ws.ctr, ws.pcell, ws.rank,
                        ws.cell_count, ws.sums_cells);
     mark(2);
-    hipLaunchKernelGGL(k_scan_tiles<unsigned int>, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream,
-                       ws.cell_count, ws.cells, ws.sums_cells, ws.cell_start);
+    hipLaunchKernelGGL(k_scan_cells, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream, ws.cell_count, ws.cells,
+                       ws.sums_cells, ws.tiles_cells_n, ws.cell_start, ws.wave_start, a.search_blocks * kWaves,
+                       ws.rows);
     mark(3);
     switch (a.dpad) {
         case 4: launch_rows<4>(a, ws, vec4); break;
