@@ -29,6 +29,7 @@ constexpr int kMaxSearchBlocks = 8192;
 // loads), in queries, when the queries are divided among the waves by work.
 constexpr unsigned int kTileWeight = 4;
 constexpr int kKeysBlock = 1024;     // threads per workgroup of the key/histogram pass
+constexpr long long kKeysTwoFrom = 196608;  // events above this many rows: two points per thread in k_keys
 constexpr int kPlaceBlock = 256;     // threads per workgroup of the placement pass
 constexpr int kPlaceTile = 256;      // queries per workgroup of the placement pass (and kept tile)
 constexpr int kKeptGroup = 64;       // kept tiles per second-level total

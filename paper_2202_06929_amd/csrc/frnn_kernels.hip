@@ -484,7 +484,10 @@ __device__ __forceinline__ unsigned int cell_key(const int (&u)[kMaxAxes], const
 constexpr int kMaxCellTiles = ((1 << 24) + kScanTile - 1) / kScanTile + 2;
 
 // Grid (blocks, n_events) of kKeysBlock threads: block 0 of event e derives and
-// stores its plan; every block computes the cells of a share of the event's rows.
+// stores its plan; every block computes the cells of kKeysBlock x kKeysPer of the
+// event's rows.  Two points per thread halve the blocks, and with them the
+// blocks' atomic adds to each tile total, which pays for large events.
+template <int kKeysPer>
 __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
                                                      float r, int cell_div, const EventDesc *__restrict__ ev,
                                                      EventDesc ev0, int ev_from_arg,
@@ -499,17 +502,22 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
     __shared__ unsigned long long tile_count[kMaxCellTiles];
     const int e = blockIdx.y;
     const EventDesc E = ev_from_arg ? ev0 : ev[e];  // one event: no load before the points'
-    if (blockIdx.x != 0 && static_cast<long long>(blockIdx.x) * kKeysBlock >= E.n) return;
-    // One point per thread; its binned coordinates are loaded before the plan is
-    // derived so that the two latencies overlap.
-    const int i = blockIdx.x * kKeysBlock + threadIdx.x;
-    const bool live = i < E.n;
-    float x[kMaxAxes] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (live) {
-        const float *row = E.pts + static_cast<size_t>(i) * d;
+    constexpr int kSpan = kKeysBlock * kKeysPer;
+    if (blockIdx.x != 0 && static_cast<long long>(blockIdx.x) * kSpan >= E.n) return;
+    // kKeysPer points per thread, kKeysBlock apart; their binned coordinates are
+    // loaded before the plan is derived so that the two latencies overlap.
+    float x[kKeysPer][kMaxAxes];
 #pragma unroll
-        for (int p = 0; p < kMaxAxes; ++p)
-            if (p < axes) x[p] = row[dd.c[p]];
+    for (int m = 0; m < kKeysPer; ++m) {
+        const int i = blockIdx.x * kSpan + m * kKeysBlock + threadIdx.x;
+#pragma unroll
+        for (int p = 0; p < kMaxAxes; ++p) x[m][p] = 0.0f;
+        if (i < E.n) {
+            const float *row = E.pts + static_cast<size_t>(i) * d;
+#pragma unroll
+            for (int p = 0; p < kMaxAxes; ++p)
+                if (p < axes) x[m][p] = row[dd.c[p]];
+        }
     }
     if (wave_id() == 0)
         derive_plan(part + static_cast<size_t>(e) * nparts, nparts, r, cell_div, axes, E.cells_max, &P);
@@ -522,17 +530,26 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
         if (P.abort) atomicOr(&ctr->abort, 1u);
     }
     if (P.abort) return;
-    if (live) {
+    unsigned int k[kKeysPer], rk[kKeysPer];
+#pragma unroll
+    for (int m = 0; m < kKeysPer; ++m) {
+        const int i = blockIdx.x * kSpan + m * kKeysBlock + threadIdx.x;
+        if (i >= E.n) continue;
         const long long gi = E.row0 + i;
         int u[kMaxAxes];
 #pragma unroll
-        for (int p = 0; p < kMaxAxes; ++p) u[p] = cell_coord(x[p], P.lo[p], P.inv_c[p], P.G[p]);
-        const unsigned int k = static_cast<unsigned int>(E.cell0) + cell_key(u, P);
+        for (int p = 0; p < kMaxAxes; ++p) u[p] = cell_coord(x[m][p], P.lo[p], P.inv_c[p], P.G[p]);
+        k[m] = static_cast<unsigned int>(E.cell0) + cell_key(u, P);
         pcell[gi] = pack_cell(u, axes);
-        const unsigned int rk = atomicAdd(&cell_count[k], 1u);
-        rank[gi] = rk;
+        rk[m] = atomicAdd(&cell_count[k[m]], 1u);
+    }
+#pragma unroll
+    for (int m = 0; m < kKeysPer; ++m) {
+        const int i = blockIdx.x * kSpan + m * kKeysBlock + threadIdx.x;
+        if (i >= E.n) continue;
+        rank[E.row0 + i] = rk[m];
         // The first point of a cell (rank 0) also counts the cell as occupied.
-        atomicAdd(&tile_count[k / kScanTile - E.tile0], rk == 0u ? (1ull << 32) | 1ull : 1ull);
+        atomicAdd(&tile_count[k[m] / kScanTile - E.tile0], rk[m] == 0u ? (1ull << 32) | 1ull : 1ull);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ntiles; t += kKeysBlock)
@@ -540,6 +557,15 @@ __global__ __launch_bounds__(kKeysBlock) void k_keys(int d, Dims dd, int axes,
 }
 
 // ------------------------------------------------------------------- scans
+
+// floor(a / b) for a < 2^52, b > 0: the quotient rounded in double is within one
+// of the exact, and integer products settle it.
+__device__ __forceinline__ unsigned long long floor_div(unsigned long long a, unsigned long long b) {
+    unsigned long long f = static_cast<unsigned long long>(static_cast<double>(a) / static_cast<double>(b));
+    if (f * b > a) --f;
+    if ((f + 1) * b <= a) ++f;
+    return f;
+}
 
 // cell_start[c] = points in cells [0, c) for c in [0, cells]; sums[t] holds tile
 // t's points (low word) and occupied cells (high word).  The tile's counts are
@@ -563,12 +589,25 @@ __global__ __launch_bounds__(kBlock) void k_scan_cells(const unsigned int *__res
     const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
     if (base > len) return;
     constexpr int kPer = kScanTile / kBlock;
+    static_assert(kPer % 4 == 0, "a thread's counts are read as 16-byte groups");
+    // A thread's kPer counts are consecutive (16-byte aligned: the tile and the
+    // workspace arrays are): whole groups are read as uint4, the last thread's
+    // partial group one by one.
     unsigned int v[kPer];
     const long long first = base + static_cast<long long>(threadIdx.x) * kPer;
+    if (first + kPer <= len) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(in + first);
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const long long idx = first + j;
-        v[j] = idx < len ? in[idx] : 0u;
+        for (int j = 0; j < kPer / 4; ++j) {
+            const uint4 g = src[j];
+            v[4 * j] = g.x;
+            v[4 * j + 1] = g.y;
+            v[4 * j + 2] = g.z;
+            v[4 * j + 3] = g.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) v[j] = first + j < len ? in[first + j] : 0u;
     }
     // Points and weight of the tiles before this one, and the weight of them all.
     unsigned long long c_before = 0, w_before = 0, w_all = 0;
@@ -609,35 +648,53 @@ __global__ __launch_bounds__(kBlock) void k_scan_cells(const unsigned int *__res
     pre += inc - mine;
     unsigned long long run_c = cb + (pre & 0xffffffffull), run_w = wb + (pre >> 32);
     const unsigned long long nw = static_cast<unsigned long long>(n_waves);
-    // Wave k starts at weight B_k = floor(k W / nw) = k q + floor(k m / nw): walk
-    // the waves whose starts fall in this thread's cells, stepping B_k without
-    // dividing.
-    const unsigned long long q = W ? W / nw : 0ull, m = W ? W % nw : 0ull;
-    unsigned long long k = W ? (run_w * nw + W - 1) / W : nw;  // the first B_k >= run_w
-    if (k == 0) k = 1;                                         // wave 0 starts at row 0
-    unsigned long long B = k * q + (k * m) / nw, frac = (k * m) % nw;
+    // Wave k starts at weight B_k = floor(k W / nw).  The thread's first wave is the
+    // smallest k with k W >= run_w nw (then B_k >= run_w); later ones follow by
+    // B_{k+1} = B_k + q + carry, with W = q nw + m and the remainder of k W / nw
+    // carried, so no division runs per wave.
+    unsigned int starts[kPer];
+    unsigned long long k = nw, B = 0, rem = 0, q = 0, m = 0;
+    if (W) {
+        q = floor_div(W, nw);
+        m = W - q * nw;
+        const unsigned long long target = run_w * nw;
+        k = floor_div(target + W - 1, W);
+        if (k == 0) k = 1;  // wave 0 starts at row 0
+        B = floor_div(k * W, nw);
+        rem = k * W - B * nw;
+    }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
-        const long long idx = first + j;
-        if (idx <= len) out[idx] = static_cast<unsigned int>(run_c);
+        starts[j] = static_cast<unsigned int>(run_c);
         const unsigned long long w = v[j] + (v[j] ? kTileWeight : 0u);
         for (; k < nw && B < run_w + w; ++k) {
             // B lies in this cell: past its fixed cost, one weight unit per query.
             const unsigned long long past = B - run_w;
             wave_start[k] = static_cast<unsigned int>(run_c + (past > kTileWeight ? past - kTileWeight : 0ull));
             B += q;
-            frac += m;
-            if (frac >= nw) {
-                frac -= nw;
+            rem += m;
+            if (rem >= nw) {
+                rem -= nw;
                 ++B;
             }
         }
         run_c += v[j];
         run_w += w;
     }
+    // cell_start has len + 1 entries: whole groups as uint4, the rest one by one.
+    if (first + kPer <= len + 1) {
+        uint4 *dst = reinterpret_cast<uint4 *>(out + first);
+#pragma unroll
+        for (int j = 0; j < kPer / 4; ++j)
+            dst[j] = make_uint4(starts[4 * j], starts[4 * j + 1], starts[4 * j + 2], starts[4 * j + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (first + j <= len) out[first + j] = starts[j];
+    }
     if (blockIdx.x == 0) {
         if (W == 0) {  // no rows: every share is empty
-            for (int k = threadIdx.x; k <= n_waves; k += kBlock) wave_start[k] = 0u;
+            for (int t = threadIdx.x; t <= n_waves; t += kBlock) wave_start[t] = 0u;
         } else if (threadIdx.x == 0) {
             wave_start[0] = 0u;
             wave_start[n_waves] = static_cast<unsigned int>(rows);
@@ -1681,8 +1738,9 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
         if (a.events) (void)hipEventRecord(a.events[stage], a.stream);
     };
     const int vec4 = a.vec4;
-    const long long kb = (static_cast<long long>(a.max_n) + kKeysBlock - 1) / kKeysBlock;
-    const int gkeys = static_cast<int>(kb < 1 ? 1 : kb);  // one point per thread
+    const int keys_per = a.max_n > kKeysTwoFrom ? 2 : 1;  // points per thread
+    const long long kb = (static_cast<long long>(a.max_n) + kKeysBlock * keys_per - 1) / (kKeysBlock * keys_per);
+    const int gkeys = static_cast<int>(kb < 1 ? 1 : kb);
     Dims dd;
     for (int p = 0; p < kMaxAxes; ++p) dd.c[p] = p < a.axes ? a.dims[p] : -1;
     mark(0);
@@ -1690,9 +1748,14 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
                        ws.ev, a.ev0, a.ev_from_arg, ws.part, ws.cell_count, ws.cells, ws.sums_cells,
                        ws.tiles_cells_n, ws.sums_kept2, ws.groups_kept_n, ws.ctr);
     mark(1);
-    hipLaunchKernelGGL(k_keys, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.d, dd, a.axes, a.r,
-                       a.cell_div, ws.ev, a.ev0, a.ev_from_arg, ws.part, a.bounds_blocks, ws.plans, ws.ctr, ws.pcell, ws.rank,
-                       ws.cell_count, ws.sums_cells);
+    if (keys_per == 2)
+        hipLaunchKernelGGL(k_keys<2>, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.d, dd, a.axes,
+                           a.r, a.cell_div, ws.ev, a.ev0, a.ev_from_arg, ws.part, a.bounds_blocks, ws.plans, ws.ctr,
+                           ws.pcell, ws.rank, ws.cell_count, ws.sums_cells);
+    else
+        hipLaunchKernelGGL(k_keys<1>, dim3(gkeys, a.n_events), dim3(kKeysBlock), 0, a.stream, a.d, dd, a.axes,
+                           a.r, a.cell_div, ws.ev, a.ev0, a.ev_from_arg, ws.part, a.bounds_blocks, ws.plans, ws.ctr,
+                           ws.pcell, ws.rank, ws.cell_count, ws.sums_cells);
     mark(2);
     hipLaunchKernelGGL(k_scan_cells, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream, ws.cell_count, ws.cells,
                        ws.sums_cells, ws.tiles_cells_n, ws.cell_start, ws.wave_start, a.search_blocks * kWaves,
