@@ -196,7 +196,8 @@ Workspace layout(void *base, long long rows, long long cells, int n_events, int 
     ws.temp = cv.take<unsigned int>(static_cast<size_t>(rows) * kListCap);
     ws.tested = cv.take<unsigned long long>(2 * kMaxSearchBlocks);
     ws.capped_blk = cv.take<unsigned int>(kMaxSearchBlocks);
-    ws.wave_start = cv.take<unsigned int>(static_cast<size_t>(kMaxSearchBlocks) * kWaves + 1);
+    ws.wave_start = cv.take<unsigned int>(static_cast<size_t>(kMaxSearchBlocks) * kWaves * kMaxPieces + 1);
+    ws.claims = cv.take<unsigned int>(8 * kPools * kPoolStride);
     ws.rows = rows;
     ws.cells = cells;
     ws.tiles_cells_n = static_cast<int>(tiles_cells);

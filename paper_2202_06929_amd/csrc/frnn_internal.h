@@ -28,6 +28,18 @@ constexpr int kMaxSearchBlocks = 8192;
 // A cell's fixed cost in the search (its runs' bounds, its candidates' first
 // loads), in queries, when the queries are divided among the waves by work.
 constexpr unsigned int kTileWeight = 4;
+// The search's queries are cut into search_pieces(DP) pieces of equal work per
+// wave: each wave takes one piece of its XCD's share, then claims the share's
+// other pieces one at a time from kPools counters per XCD, so that waves that
+// finish early take work from the others.  Rows of up to 8 floats keep one piece
+// per wave: their queries cost about the same, and the claims and the cells cut
+// twice cost more than they even out (the 120k-point 8-D search took 34.9 us with
+// two pieces against 30.9 with one); wider rows take two (the 300k-point 12-D
+// search: 114.5 us against 118.5).
+constexpr int kMaxPieces = 2;
+constexpr int search_pieces(int dpad) { return dpad <= 8 ? 1 : 2; }
+constexpr int kPools = 8;
+constexpr int kPoolStride = 32;  // counters 128 bytes apart
 constexpr int kKeysBlock = 1024;     // threads per workgroup of the key/histogram pass
 constexpr long long kKeysTwoFrom = 196608;  // events above this many rows: two points per thread in k_keys
 constexpr int kPlaceBlock = 256;     // threads per workgroup of the placement pass
@@ -124,7 +136,8 @@ struct Workspace {
     unsigned int *temp;         // [rows * kListCap] neighbour lists of up to kListCap entries
     unsigned long long *tested; // [2 kMaxSearchBlocks] pairs examined, then pairs fully tested, per search workgroup
     unsigned int *capped_blk;   // [kMaxSearchBlocks] capped queries per search workgroup
-    unsigned int *wave_start;   // [kMaxSearchBlocks kWaves + 1] first sorted row of each search wave's share
+    unsigned int *wave_start;   // [kMaxSearchBlocks kWaves kMaxPieces + 1] first sorted row of each search piece
+    unsigned int *claims;       // [8 kPools kPoolStride] the search's piece counters, cleared by the cell scan
     long long rows;
     long long cells;
     int tiles_cells_n;

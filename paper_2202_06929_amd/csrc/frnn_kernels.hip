@@ -572,7 +572,7 @@ __device__ __forceinline__ unsigned long long floor_div(unsigned long long a, un
 // requested before the totals of the tiles before it are summed, so that the two
 // round trips overlap.
 //
-// The same pass divides the queries among the search's n_waves waves by work
+// The same pass divides the queries into the search's n_waves pieces by work
 // rather than by count: a cell weighs its points plus kTileWeight if it has any
 // (a tile's fixed cost, in queries), the cells in order span weights [0, W), and
 // wave k starts at weight floor(k W / n_waves), which falls in one cell; the wave
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_cells(const unsigned int *__res
                                                        const unsigned long long *__restrict__ sums, int tiles,
                                                        unsigned int *__restrict__ out,
                                                        unsigned int *__restrict__ wave_start, int n_waves,
-                                                       long long rows) {
+                                                       long long rows, unsigned int *__restrict__ claims) {
     __shared__ unsigned long long red[4 * kWaves];
     const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
     if (base > len) return;
@@ -693,6 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_cells(const unsigned int *__res
             if (first + j <= len) out[first + j] = starts[j];
     }
     if (blockIdx.x == 0) {
+        if (threadIdx.x < 8 * kPools) claims[threadIdx.x * kPoolStride] = 0u;
         if (W == 0) {  // no rows: every share is empty
             for (int t = threadIdx.x; t <= n_waves; t += kBlock) wave_start[t] = 0u;
         } else if (threadIdx.x == 0) {
@@ -836,6 +837,7 @@ template <int DP, bool SEL>
 __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float *__restrict__ sorted,
                                                    const unsigned int *__restrict__ sorted_id,
                                                    const unsigned int *__restrict__ wave_start,
+                                                   unsigned int *__restrict__ claims,
                                                    const EventDesc *__restrict__ ev, int n_events,
                                                    const unsigned int *__restrict__ cell_start,
                                                    const Plan *__restrict__ plans, float r2, int K,
@@ -891,19 +893,29 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned long long tested = 0;
     unsigned long long survived = 0;
 
-    // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that the
-    // workgroups of one XCD take consecutive queries and share their rows in its L2.
-    // Each wave takes a contiguous share of the queries in cell order of equal work
-    // (its cells' fixed costs plus its queries, divided by the cell scan; a share
-    // may start or end inside a cell, so a dense cell is split across waves instead
-    // of holding up one wave).
+    // The cell scan cuts the queries, in cell order, into kPieces pieces of equal
+    // work per wave (one for rows of up to 8 floats, two for wider ones) (its cells' fixed costs plus its queries; a piece may start or
+    // end inside a cell, so a dense cell is split instead of holding up one wave).
+    // Workgroups are dealt to the 8 XCDs round-robin; the workgroups of one XCD
+    // take a contiguous share of the pieces, so that they share their rows in its
+    // L2: each wave first takes one piece of the share, then claims the share's
+    // remaining pieces one at a time from one of the XCD's counters (workgroup w
+    // of the XCD uses counter w mod kPools, which hands out every kPools-th piece),
+    // so that a wave that finishes early takes work the others have not started.
+    // A wave's pieces only move forward in row order.  With one piece per wave
+    // the claims compile out.
+    constexpr int kPieces = search_pieces(DP);
     const unsigned int nb = gridDim.x;
     const unsigned int xcd = blockIdx.x % 8u, per = nb / 8u, rest = nb % 8u;
-    const unsigned int lb = xcd < rest ? xcd * (per + 1u) + blockIdx.x / 8u
-                                       : rest * (per + 1u) + (xcd - rest) * per + blockIdx.x / 8u;
-    const unsigned int gw = lb * kWaves + wave_id();
-    const unsigned int q_lo = wave_start[gw];
-    const unsigned int q_hi = wave_start[gw + 1u];
+    const unsigned int xnb = per + (xcd < rest ? 1u : 0u);  // workgroups on this XCD
+    const unsigned int xb0 = xcd < rest ? xcd * (per + 1u) : rest * (per + 1u) + (xcd - rest) * per;
+    const unsigned int xblk = blockIdx.x / 8u;              // this workgroup's number on its XCD
+    const unsigned int x_first = kPieces * kWaves * xb0;    // the XCD's first piece
+    const unsigned int x_dyn = x_first + kWaves * xnb;      // its first claimed piece
+    const unsigned int x_end = x_first + kPieces * kWaves * xnb;
+    const unsigned int pools = min(static_cast<unsigned int>(kPools), xnb);
+    const unsigned int pool = xblk % pools;
+    unsigned int *claim = claims + (xcd * kPools + pool) * kPoolStride;
     Plan P;
     RunLane rl;
     unsigned int cell0 = 0;
@@ -912,268 +924,279 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     // The share is read in windows of 64 queries: lane l holds query win + l (its
     // original row and packed cell), and a tile is a run of consecutive lanes with the
     // same cell, found by a ballot (no per-tile lookup of where the cell ends).
-    for (unsigned int win = q_lo; win < q_hi;) {
-        const unsigned int nwin = min(64u, q_hi - win);
-        uint2 me = make_uint2(0u, 0u);
-        if (static_cast<unsigned int>(lane) < nwin) me = sid[win + lane];
-        const unsigned int v_orig = me.x, v_pc = me.y;
-        for (unsigned int t0 = 0; t0 < nwin;) {
-            const unsigned int qs = win + t0;
-            if (qs >= ev_end) {
-                const int e = n_events == 1 ? 0 : find_event(ev, n_events, qs);
-                P = plans[e];
-                const EventDesc E = ev[e];
-                cell0 = static_cast<unsigned int>(E.cell0);
-                ev_end = static_cast<unsigned int>(E.row0) + static_cast<unsigned int>(E.n);
-                rl = run_lane(P);
-            }
-            const unsigned int pc = __builtin_amdgcn_readlane(v_pc, t0);
-            const unsigned long long other =
-                __builtin_amdgcn_ballot_w64(static_cast<unsigned int>(lane) >= nwin || v_pc != pc) &
-                (~0ull << t0);
-            unsigned int t1 = other ? static_cast<unsigned int>(__builtin_ctzll(other)) : 64u;
-            t1 = min(t1, ev_end - win);  // a tile never crosses into the next event
-            const unsigned int qe = win + t1;
-            int u[kMaxAxes];
-            unpack_cell(pc, P.axes, u);
-            unsigned int start, pre, end;
-            const unsigned int M = wave_runs(u, cell0, P, rl, cell_start, start, pre, end);
-            for (unsigned int q0 = qs; q0 < qe; q0 += kQT) {
-                const int Qn = static_cast<int>(uniform(min(static_cast<unsigned int>(kQT), qe - q0)));
-                if (prio) {
-                    // A SIMD issues the oldest ready wave first, so with every workgroup
-                    // resident from the start the waves dispatched last finish last and
-                    // the SIMD runs its final stretch with few waves.  Issue priority
-                    // falls as a wave works off its share (3 in the first quarter, 0 in
-                    // the last), so that waves behind are issued first and the waves of
-                    // a SIMD finish closer together.
-                    const unsigned int left = q_hi - q0;
-                    const unsigned int share = q_hi - q_lo;
-                    if (4u * left > 3u * share) __builtin_amdgcn_s_setprio(3);
-                    else if (4u * left > 2u * share) __builtin_amdgcn_s_setprio(2);
-                    else if (4u * left > share) __builtin_amdgcn_s_setprio(1);
-                    else __builtin_amdgcn_s_setprio(0);
+    for (unsigned int piece = x_first + xblk * kWaves + wave_id(); piece < x_end;) {
+        // The next piece is claimed before this one is worked off, so that the claim's
+        // round trip overlaps the first loads.
+        unsigned int claimed = 0;
+        if (kPieces > 1 && lane == 0) claimed = atomicAdd(claim, 1u);
+        const unsigned int q_lo = wave_start[piece];
+        const unsigned int q_hi = wave_start[piece + 1u];
+        for (unsigned int win = q_lo; win < q_hi;) {
+            const unsigned int nwin = min(64u, q_hi - win);
+            uint2 me = make_uint2(0u, 0u);
+            if (static_cast<unsigned int>(lane) < nwin) me = sid[win + lane];
+            const unsigned int v_orig = me.x, v_pc = me.y;
+            for (unsigned int t0 = 0; t0 < nwin;) {
+                const unsigned int qs = win + t0;
+                if (qs >= ev_end) {
+                    const int e = n_events == 1 ? 0 : find_event(ev, n_events, qs);
+                    P = plans[e];
+                    const EventDesc E = ev[e];
+                    cell0 = static_cast<unsigned int>(E.cell0);
+                    ev_end = static_cast<unsigned int>(E.row0) + static_cast<unsigned int>(E.n);
+                    rl = run_lane(P);
                 }
-                if (lane < kQT) qcnt[lane] = 0u;
-                // Candidate rows are fetched one chunk ahead so that their latency
-                // overlaps the tests of the current chunk (with row-addressed ring entries
-                // only the leading coordinates, one 16-byte load).  Idle lanes read row 0
-                // (any row is a valid address) and are masked out of every ballot.
-                constexpr int kHeld = kRowRing ? 4 : DP;  // candidate coordinates held per lane
-                float cn[kHeld];
-                unsigned int sn, jn = 0u;
-                // Candidate b + lane lies in the last run that starts at or before it:
-                // each run that starts inside the chunk marks its first lane (the run
-                // holding candidate b marks lane 0) and a prefix maximum spreads the
-                // marks over the lanes after them.
-                auto fetch = [&](unsigned int b) {
-                    wave_lds_sync();
-                    mark[lane] = 0u;
-                    wave_lds_sync();
-                    if (end > pre && pre < b + 64u && end > b) mark[pre > b ? pre - b : 0u] = lane + 1u;
-                    wave_lds_sync();
-                    const int r = static_cast<int>(wave_scan_max(mark[lane])) - 1;
-                    const unsigned int mm = b + lane;
-                    const unsigned int srow = static_cast<unsigned int>(__shfl(start, r)) +
-                                              (mm - static_cast<unsigned int>(__shfl(pre, r)));
-                    sn = mm < M ? srow : 0u;
-                    if constexpr (kRowRing) {
-                        const float4 v = *reinterpret_cast<const float4 *>(sorted + static_cast<size_t>(sn) * DP);
-                        cn[0] = v.x;
-                        cn[1] = v.y;
-                        cn[2] = v.z;
-                        cn[3] = v.w;
-                    } else {
-                        load_row<DP>(sorted, sn, cn);
-                        jn = sorted_id[2u * sn];
+                const unsigned int pc = __builtin_amdgcn_readlane(v_pc, t0);
+                const unsigned long long other =
+                    __builtin_amdgcn_ballot_w64(static_cast<unsigned int>(lane) >= nwin || v_pc != pc) &
+                    (~0ull << t0);
+                unsigned int t1 = other ? static_cast<unsigned int>(__builtin_ctzll(other)) : 64u;
+                t1 = min(t1, ev_end - win);  // a tile never crosses into the next event
+                const unsigned int qe = win + t1;
+                int u[kMaxAxes];
+                unpack_cell(pc, P.axes, u);
+                unsigned int start, pre, end;
+                const unsigned int M = wave_runs(u, cell0, P, rl, cell_start, start, pre, end);
+                for (unsigned int q0 = qs; q0 < qe; q0 += kQT) {
+                    const int Qn = static_cast<int>(uniform(min(static_cast<unsigned int>(kQT), qe - q0)));
+                    if (prio) {
+                        // A SIMD issues the oldest ready wave first, so with every workgroup
+                        // resident from the start the waves dispatched last finish last and
+                        // the SIMD runs its final stretch with few waves.  Issue priority
+                        // falls as a wave works off its share (3 in the first quarter, 0 in
+                        // the last), so that waves behind are issued first and the waves of
+                        // a SIMD finish closer together.
+                        const unsigned int left = q_hi - q0;
+                        const unsigned int share = q_hi - q_lo;
+                        if (4u * left > 3u * share) __builtin_amdgcn_s_setprio(3);
+                        else if (4u * left > 2u * share) __builtin_amdgcn_s_setprio(2);
+                        else if (4u * left > share) __builtin_amdgcn_s_setprio(1);
+                        else __builtin_amdgcn_s_setprio(0);
                     }
-                    // Lanes past the last candidate fail every first-stage test.
-                    if (mm >= M) cn[0] = INFINITY;
-                };
-                // A pair that passes the full test joins query q's list.
-                auto keep = [&](bool pass, unsigned int q, unsigned int j, float D) {
-                    if (pass) {
-                        const unsigned int pos = atomicAdd(&qcnt[q], 1u);
-                        if (pos < static_cast<unsigned int>(kListCap)) {
-                            lst[q * kListCap + pos] = j;
-                            if (SEL) lstd[q * kListCap + pos] = __float_as_uint(D);
-                        }
-                    }
-                };
-                // Second stage for ring entries [h, h + nb): lane l takes entry h + l and
-                // adds terms kLead.. of the definition to the first stage's partial sum,
-                // in the same order.  A row-addressed entry names its candidate row (the
-                // remaining coordinates are loaded); a lane-addressed entry (below) names
-                // the lane of the current chunk that holds the candidate.
-                auto finish_rows = [&](unsigned int h, unsigned int nb) {
-                    wave_lds_sync();
-                    const bool act = static_cast<unsigned int>(lane) < nb;
-                    const unsigned int e = (h + lane) & (kRing - 1);
-                    const unsigned long long ent = act ? ring[e] : 0ull;
-                    const float a3 = act ? racc[e] : 0.0f;
-                    const unsigned int q = static_cast<unsigned int>(ent >> 32);
-                    const unsigned int s2 = static_cast<unsigned int>(ent);
-                    const float *crow = sorted + static_cast<size_t>(s2) * DP;
-                    float cc[DP];
-#pragma unroll
-                    for (int k = kLead; k < DP; ++k) cc[k] = crow[k];
-                    const unsigned int j2 = sorted_id[2u * s2];
-                    const float D = add_terms<kLead, DP, DP>(a3, cc, sorted + static_cast<size_t>(q0 + q) * DP);
-                    keep(act && D < r2 && s2 != q0 + q, q, j2, D);
-                    wave_lds_sync();
-                };
-                fetch(0u);
-                unsigned int head = 0, tail = 0;
-                for (unsigned int base = 0; base < M; base += 64) {
-                    float c[kHeld];
-#pragma unroll
-                    for (int k = 0; k < kHeld; ++k) c[k] = cn[k];
-                    const unsigned int s = sn, jid = jn;
-                    if (base + 64 < M) fetch(base + 64);
-                    // Lane-addressed entries: the candidate's coordinates are exchanged
-                    // between lanes of the current chunk.
-                    auto finish = [&](unsigned int h, unsigned int nb) {
+                    if (lane < kQT) qcnt[lane] = 0u;
+                    // Candidate rows are fetched one chunk ahead so that their latency
+                    // overlaps the tests of the current chunk (with row-addressed ring entries
+                    // only the leading coordinates, one 16-byte load).  Idle lanes read row 0
+                    // (any row is a valid address) and are masked out of every ballot.
+                    constexpr int kHeld = kRowRing ? 4 : DP;  // candidate coordinates held per lane
+                    float cn[kHeld];
+                    unsigned int sn, jn = 0u;
+                    // Candidate b + lane lies in the last run that starts at or before it:
+                    // each run that starts inside the chunk marks its first lane (the run
+                    // holding candidate b marks lane 0) and a prefix maximum spreads the
+                    // marks over the lanes after them.
+                    auto fetch = [&](unsigned int b) {
+                        wave_lds_sync();
+                        mark[lane] = 0u;
+                        wave_lds_sync();
+                        if (end > pre && pre < b + 64u && end > b) mark[pre > b ? pre - b : 0u] = lane + 1u;
+                        wave_lds_sync();
+                        const int r = static_cast<int>(wave_scan_max(mark[lane])) - 1;
+                        const unsigned int mm = b + lane;
+                        const unsigned int srow = static_cast<unsigned int>(__shfl(start, r)) +
+                                                  (mm - static_cast<unsigned int>(__shfl(pre, r)));
+                        sn = mm < M ? srow : 0u;
                         if constexpr (kRowRing) {
-                            finish_rows(h, nb);
+                            const float4 v = *reinterpret_cast<const float4 *>(sorted + static_cast<size_t>(sn) * DP);
+                            cn[0] = v.x;
+                            cn[1] = v.y;
+                            cn[2] = v.z;
+                            cn[3] = v.w;
                         } else {
-                            wave_lds_sync();
-                            const bool act = static_cast<unsigned int>(lane) < nb;
-                            const unsigned int e = (h + lane) & (kRing - 1);
-                            const unsigned long long ent = act ? ring[e] : 0ull;
-                            float cc[DP];
-                            const unsigned int code = static_cast<unsigned int>(ent >> 32);
-                            const int cl = static_cast<int>(code & 63u);
-                            const unsigned int q = code >> 6;
-#pragma unroll
-                            for (int k = kLead; k < DP; ++k) cc[k] = __shfl(c[k], cl);
-                            const unsigned int s2 = static_cast<unsigned int>(__shfl(static_cast<int>(s), cl));
-                            const unsigned int j2 = static_cast<unsigned int>(__shfl(static_cast<int>(jid), cl));
-                            const float D = add_terms<kLead, DP, DP>(__uint_as_float(static_cast<unsigned int>(ent)),
-                                                                     cc, sorted + static_cast<size_t>(q0 + q) * DP);
-                            keep(act && D < r2 && s2 != q0 + q, q, j2, D);
-                            wave_lds_sync();
+                            load_row<DP>(sorted, sn, cn);
+                            jn = sorted_id[2u * sn];
                         }
+                        // Lanes past the last candidate fail every first-stage test.
+                        if (mm >= M) cn[0] = INFINITY;
                     };
-                    // Query rows are wave-uniform (scalar loads); the next one is
-                    // requested before the current one is tested (the sorted rows end with
-                    // one padding row, so the request after the last query stays in bounds).
-                    float qn[kLead];
-#pragma unroll
-                    for (int k = 0; k < kLead; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
-                    const float *qrow = sorted + static_cast<size_t>(q0) * DP;
-                    for (int q = 0; q < Qn; ++q, qrow += DP) {
-                        float qc[kLead];
-#pragma unroll
-                        for (int k = 0; k < kLead; ++k) qc[k] = qn[k];
-#pragma unroll
-                        for (int k = 0; k < kLead; ++k) qn[k] = qrow[DP + k];
-                        // First stage: kLead terms for all 64 candidates; pairs that are not
-                        // yet at r2 are queued (exact: the remaining terms only add).
-                        const float acc = add_terms_r<0, kLead, kHeld, kLead>(0.0f, c, qc);
-                        const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2);
-                        if (m1 == 0ull) continue;
-                        if (acc < r2) {
-                            ++survived;
-                            const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
-                            if constexpr (kRowRing) {
-                                ring[e] = (static_cast<unsigned long long>(uniform(static_cast<unsigned int>(q))) << 32) | s;
-                                racc[e] = acc;
-                            } else {
-                                ring[e] = (static_cast<unsigned long long>((static_cast<unsigned int>(q) << 6) |
-                                                                          static_cast<unsigned int>(lane)) << 32) |
-                                          __float_as_uint(acc);
+                    // A pair that passes the full test joins query q's list.
+                    auto keep = [&](bool pass, unsigned int q, unsigned int j, float D) {
+                        if (pass) {
+                            const unsigned int pos = atomicAdd(&qcnt[q], 1u);
+                            if (pos < static_cast<unsigned int>(kListCap)) {
+                                lst[q * kListCap + pos] = j;
+                                if (SEL) lstd[q * kListCap + pos] = __float_as_uint(D);
                             }
                         }
-                        tail += static_cast<unsigned int>(__popcll(m1));
-                        if (tail - head >= 64u) {
-                            finish(head, 64u);
-                            head += 64u;
+                    };
+                    // Second stage for ring entries [h, h + nb): lane l takes entry h + l and
+                    // adds terms kLead.. of the definition to the first stage's partial sum,
+                    // in the same order.  A row-addressed entry names its candidate row (the
+                    // remaining coordinates are loaded); a lane-addressed entry (below) names
+                    // the lane of the current chunk that holds the candidate.
+                    auto finish_rows = [&](unsigned int h, unsigned int nb) {
+                        wave_lds_sync();
+                        const bool act = static_cast<unsigned int>(lane) < nb;
+                        const unsigned int e = (h + lane) & (kRing - 1);
+                        const unsigned long long ent = act ? ring[e] : 0ull;
+                        const float a3 = act ? racc[e] : 0.0f;
+                        const unsigned int q = static_cast<unsigned int>(ent >> 32);
+                        const unsigned int s2 = static_cast<unsigned int>(ent);
+                        const float *crow = sorted + static_cast<size_t>(s2) * DP;
+                        float cc[DP];
+    #pragma unroll
+                        for (int k = kLead; k < DP; ++k) cc[k] = crow[k];
+                        const unsigned int j2 = sorted_id[2u * s2];
+                        const float D = add_terms<kLead, DP, DP>(a3, cc, sorted + static_cast<size_t>(q0 + q) * DP);
+                        keep(act && D < r2 && s2 != q0 + q, q, j2, D);
+                        wave_lds_sync();
+                    };
+                    fetch(0u);
+                    unsigned int head = 0, tail = 0;
+                    for (unsigned int base = 0; base < M; base += 64) {
+                        float c[kHeld];
+    #pragma unroll
+                        for (int k = 0; k < kHeld; ++k) c[k] = cn[k];
+                        const unsigned int s = sn, jid = jn;
+                        if (base + 64 < M) fetch(base + 64);
+                        // Lane-addressed entries: the candidate's coordinates are exchanged
+                        // between lanes of the current chunk.
+                        auto finish = [&](unsigned int h, unsigned int nb) {
+                            if constexpr (kRowRing) {
+                                finish_rows(h, nb);
+                            } else {
+                                wave_lds_sync();
+                                const bool act = static_cast<unsigned int>(lane) < nb;
+                                const unsigned int e = (h + lane) & (kRing - 1);
+                                const unsigned long long ent = act ? ring[e] : 0ull;
+                                float cc[DP];
+                                const unsigned int code = static_cast<unsigned int>(ent >> 32);
+                                const int cl = static_cast<int>(code & 63u);
+                                const unsigned int q = code >> 6;
+    #pragma unroll
+                                for (int k = kLead; k < DP; ++k) cc[k] = __shfl(c[k], cl);
+                                const unsigned int s2 = static_cast<unsigned int>(__shfl(static_cast<int>(s), cl));
+                                const unsigned int j2 = static_cast<unsigned int>(__shfl(static_cast<int>(jid), cl));
+                                const float part = __uint_as_float(static_cast<unsigned int>(ent));
+                                const float D =
+                                    add_terms<kLead, DP, DP>(part, cc, sorted + static_cast<size_t>(q0 + q) * DP);
+                                keep(act && D < r2 && s2 != q0 + q, q, j2, D);
+                                wave_lds_sync();
+                            }
+                        };
+                        // Query rows are wave-uniform (scalar loads); the next one is
+                        // requested before the current one is tested (the sorted rows end with
+                        // one padding row, so the request after the last query stays in bounds).
+                        float qn[kLead];
+    #pragma unroll
+                        for (int k = 0; k < kLead; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
+                        const float *qrow = sorted + static_cast<size_t>(q0) * DP;
+                        for (int q = 0; q < Qn; ++q, qrow += DP) {
+                            float qc[kLead];
+    #pragma unroll
+                            for (int k = 0; k < kLead; ++k) qc[k] = qn[k];
+    #pragma unroll
+                            for (int k = 0; k < kLead; ++k) qn[k] = qrow[DP + k];
+                            // First stage: kLead terms for all 64 candidates; pairs that are not
+                            // yet at r2 are queued (exact: the remaining terms only add).
+                            const float acc = add_terms_r<0, kLead, kHeld, kLead>(0.0f, c, qc);
+                            const unsigned long long m1 = __builtin_amdgcn_ballot_w64(acc < r2);
+                            if (m1 == 0ull) continue;
+                            if (acc < r2) {
+                                ++survived;
+                                const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
+                                if constexpr (kRowRing) {
+                                    const unsigned int qu = uniform(static_cast<unsigned int>(q));
+                                    ring[e] = (static_cast<unsigned long long>(qu) << 32) | s;
+                                    racc[e] = acc;
+                                } else {
+                                    ring[e] = (static_cast<unsigned long long>((static_cast<unsigned int>(q) << 6) |
+                                                                              static_cast<unsigned int>(lane)) << 32) |
+                                              __float_as_uint(acc);
+                                }
+                            }
+                            tail += static_cast<unsigned int>(__popcll(m1));
+                            if (tail - head >= 64u) {
+                                finish(head, 64u);
+                                head += 64u;
+                            }
+                        }
+                        // Lane-addressed entries refer to this chunk's registers: drain them now.
+                        if (!kRowRing && tail != head) {
+                            finish(head, tail - head);
+                            head = tail;
                         }
                     }
-                    // Lane-addressed entries refer to this chunk's registers: drain them now.
-                    if (!kRowRing && tail != head) {
-                        finish(head, tail - head);
-                        head = tail;
+                    if constexpr (kRowRing) {
+                        if (tail != head) finish_rows(head, tail - head);
                     }
-                }
-                if constexpr (kRowRing) {
-                    if (tail != head) finish_rows(head, tail - head);
-                }
-                const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
-                if (lane < Qn) tested += M;
-                // Original row of query q0 + lane, held by lane q0 + lane - win.
-                const unsigned int iq = static_cast<unsigned int>(
-                    __shfl(static_cast<int>(v_orig), static_cast<int>((q0 - win + lane) & 63u)));
-                wave_lds_sync();
-                // Kept counts for every query; lists that fit are stored at a fixed place
-                // (kListCap slots per original row); the sorted rows of longer ones are
-                // queued (one atomic each) for the placement pass to collect again.
-                const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
-                                  (SEL || cnt <= static_cast<unsigned int>(K));
-                if (lane < Qn) {
-                    const unsigned int i = iq;
-                    // Scattered stores (the count, then the list in 16-byte pieces) put
-                    // everything about query i at places indexed by i, which the placement
-                    // pass then reads in order.
-                    const unsigned int kq = min(cnt, static_cast<unsigned int>(K));
-                    kept[i] = kq | (fits ? 0u : kKeptLong);
-                    if (cnt > static_cast<unsigned int>(K)) ++capped;
-                    if (!fits) long_slots[atomicAdd(&ctr->heavy_count, 1u)] = q0 + lane;
-                }
-                // Lists that fit go to their fixed place (kListCap slots per original row)
-                // as found, in 16-byte pieces; the placement pass orders every such list
-                // by neighbour id.  With the cap binding (SEL and more than K hits), the
-                // entries of those lists are numbered through a prefix over their
-                // lengths; each lane takes one entry, finds its query by binary search,
-                // ranks it by its (D, j) key within its list (D >= 0, so its bits order
-                // like the value; keys are distinct) and, if the rank is below K, writes
-                // it at that rank: the list's first K slots then hold its K nearest.
-                const unsigned int Ku = static_cast<unsigned int>(K);
-                if (fits && !(SEL && cnt > Ku)) {
-                    const uint4 *from = reinterpret_cast<const uint4 *>(lst + lane * kListCap);
-                    uint4 *to = reinterpret_cast<uint4 *>(temp + static_cast<size_t>(iq) * kListCap);
-                    for (unsigned int k = 0; 4u * k < cnt; ++k) to[k] = from[k];
-                }
-                if (SEL) {
-                    const unsigned int take = fits && cnt > Ku ? cnt : 0u;
-                    const unsigned int inc = wave_inclusive_scan(take);
-                    const unsigned int T = __builtin_amdgcn_readlane(inc, 63);
+                    const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
+                    if (lane < Qn) tested += M;
+                    // Original row of query q0 + lane, held by lane q0 + lane - win.
+                    const unsigned int iq = static_cast<unsigned int>(
+                        __shfl(static_cast<int>(v_orig), static_cast<int>((q0 - win + lane) & 63u)));
+                    wave_lds_sync();
+                    // Kept counts for every query; lists that fit are stored at a fixed place
+                    // (kListCap slots per original row); the sorted rows of longer ones are
+                    // queued (one atomic each) for the placement pass to collect again.
+                    const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
+                                      (SEL || cnt <= static_cast<unsigned int>(K));
                     if (lane < Qn) {
-                        tpre[lane] = inc - take;
-                        tcnt[lane] = take;
-                        qorig[lane] = iq;
+                        const unsigned int i = iq;
+                        // Scattered stores (the count, then the list in 16-byte pieces) put
+                        // everything about query i at places indexed by i, which the placement
+                        // pass then reads in order.
+                        const unsigned int kq = min(cnt, static_cast<unsigned int>(K));
+                        kept[i] = kq | (fits ? 0u : kKeptLong);
+                        if (cnt > static_cast<unsigned int>(K)) ++capped;
+                        if (!fits) long_slots[atomicAdd(&ctr->heavy_count, 1u)] = q0 + lane;
+                    }
+                    // Lists that fit go to their fixed place (kListCap slots per original row)
+                    // as found, in 16-byte pieces; the placement pass orders every such list
+                    // by neighbour id.  With the cap binding (SEL and more than K hits), the
+                    // entries of those lists are numbered through a prefix over their
+                    // lengths; each lane takes one entry, finds its query by binary search,
+                    // ranks it by its (D, j) key within its list (D >= 0, so its bits order
+                    // like the value; keys are distinct) and, if the rank is below K, writes
+                    // it at that rank: the list's first K slots then hold its K nearest.
+                    const unsigned int Ku = static_cast<unsigned int>(K);
+                    if (fits && !(SEL && cnt > Ku)) {
+                        const uint4 *from = reinterpret_cast<const uint4 *>(lst + lane * kListCap);
+                        uint4 *to = reinterpret_cast<uint4 *>(temp + static_cast<size_t>(iq) * kListCap);
+                        for (unsigned int k = 0; 4u * k < cnt; ++k) to[k] = from[k];
+                    }
+                    if (SEL) {
+                        const unsigned int take = fits && cnt > Ku ? cnt : 0u;
+                        const unsigned int inc = wave_inclusive_scan(take);
+                        const unsigned int T = __builtin_amdgcn_readlane(inc, 63);
+                        if (lane < Qn) {
+                            tpre[lane] = inc - take;
+                            tcnt[lane] = take;
+                            qorig[lane] = iq;
+                        }
+                        wave_lds_sync();
+                        auto entry_query = [&](unsigned int t) {
+                            int lo = 0, hi = Qn - 1;  // last query whose list starts at or before t
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (tpre[mid] <= t) lo = mid;
+                                else hi = mid - 1;
+                            }
+                            return lo;
+                        };
+                        for (unsigned int t0 = 0; t0 < T; t0 += 64) {
+                            const unsigned int t = t0 + lane;
+                            if (t < T) {
+                                const int lo = entry_query(t);
+                                const unsigned int cq = tcnt[lo];
+                                const unsigned int *l = lst + lo * kListCap;
+                                const unsigned int *ld = lstd + lo * kListCap;
+                                const unsigned int x = t - tpre[lo];
+                                const unsigned long long key = (static_cast<unsigned long long>(ld[x]) << 32) | l[x];
+                                unsigned int sr = 0;  // the entry's rank by (D, j) in its list
+                                for (unsigned int u = 0; u < cq; ++u)
+                                    sr += ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) < key ? 1u : 0u;
+                                if (sr < Ku) temp[static_cast<size_t>(qorig[lo]) * kListCap + sr] = l[x];
+                            }
+                        }
                     }
                     wave_lds_sync();
-                    auto entry_query = [&](unsigned int t) {
-                        int lo = 0, hi = Qn - 1;  // last query whose list starts at or before t
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (tpre[mid] <= t) lo = mid;
-                            else hi = mid - 1;
-                        }
-                        return lo;
-                    };
-                    for (unsigned int t0 = 0; t0 < T; t0 += 64) {
-                        const unsigned int t = t0 + lane;
-                        if (t < T) {
-                            const int lo = entry_query(t);
-                            const unsigned int cq = tcnt[lo];
-                            const unsigned int *l = lst + lo * kListCap;
-                            const unsigned int *ld = lstd + lo * kListCap;
-                            const unsigned int x = t - tpre[lo];
-                            const unsigned long long key = (static_cast<unsigned long long>(ld[x]) << 32) | l[x];
-                            unsigned int sr = 0;  // the entry's rank by (D, j) in its list
-                            for (unsigned int u = 0; u < cq; ++u)
-                                sr += ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) < key ? 1u : 0u;
-                            if (sr < Ku) temp[static_cast<size_t>(qorig[lo]) * kListCap + sr] = l[x];
-                        }
-                    }
                 }
-                wave_lds_sync();
+                t0 = t1;
             }
-            t0 = t1;
+            win += nwin;
         }
-        win += nwin;
+        piece = kPieces > 1 ? x_dyn + pool + __builtin_amdgcn_readfirstlane(claimed) * pools : x_end;
     }
     capped = wave_sum(capped);
     tested = wave_sum(tested);
@@ -1681,12 +1704,12 @@ void launch_rows(const LaunchArgs &a, const Workspace &ws, int vec4) {
     mark(4);
     if (a.K < kListCap)
         hipLaunchKernelGGL((k_search<DP, true>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
-                           ws.sorted_id, ws.wave_start, ws.ev, a.n_events, ws.cell_start, ws.plans,
+                           ws.sorted_id, ws.wave_start, ws.claims, ws.ev, a.n_events, ws.cell_start, ws.plans,
                            a.r2, a.K, ws.kept, ws.temp, ws.long_slots, ws.ctr, ws.tested, ws.capped_blk,
                            a.search_prio);
     else
         hipLaunchKernelGGL((k_search<DP, false>), dim3(a.search_blocks), dim3(kBlock), 0, a.stream, ws.sorted,
-                           ws.sorted_id, ws.wave_start, ws.ev, a.n_events, ws.cell_start, ws.plans,
+                           ws.sorted_id, ws.wave_start, ws.claims, ws.ev, a.n_events, ws.cell_start, ws.plans,
                            a.r2, a.K, ws.kept, ws.temp, ws.long_slots, ws.ctr, ws.tested, ws.capped_blk,
                            a.search_prio);
     mark(5);
@@ -1758,8 +1781,8 @@ hipError_t enqueue_build(const LaunchArgs &a, const Workspace &ws) {
                            ws.pcell, ws.rank, ws.cell_count, ws.sums_cells);
     mark(2);
     hipLaunchKernelGGL(k_scan_cells, dim3(ws.tiles_cells_n), dim3(kBlock), 0, a.stream, ws.cell_count, ws.cells,
-                       ws.sums_cells, ws.tiles_cells_n, ws.cell_start, ws.wave_start, a.search_blocks * kWaves,
-                       ws.rows);
+                       ws.sums_cells, ws.tiles_cells_n, ws.cell_start, ws.wave_start,
+                       a.search_blocks * kWaves * search_pieces(a.dpad), ws.rows, ws.claims);
     mark(3);
     switch (a.dpad) {
         case 4: launch_rows<4>(a, ws, vec4); break;
