@@ -850,9 +850,13 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     // Queries per tile: 16 when the lists also hold distances (their LDS would
     // otherwise cost occupancy), else kQTile.
     constexpr int kQT = SEL ? 16 : kQTile;
+    static_assert((kQT & (kQT - 1)) == 0 && kQT <= 64, "list slots are numbered modulo kQT");
     __shared__ __align__(16) unsigned int lst_all[kWaves][kQT * kListCap];
     __shared__ unsigned int lstd_all[SEL ? kWaves : 1][SEL ? kQT * kListCap : 1];  // D bits of each hit
-    __shared__ unsigned int qorig_all[SEL ? kWaves : 1][SEL ? kQT : 1];           // original row of each query
+    // Per list slot (kQT per wave, taken by the queries in turn): the query's sorted
+    // and original rows.
+    __shared__ unsigned int qrow_all[kWaves][kQT];
+    __shared__ unsigned int qid_all[kWaves][kQT];
     __shared__ unsigned int pre_all[kWaves][kQT + 1];
     __shared__ unsigned int cnt_all[kWaves][kQT];
     __shared__ unsigned int qcnt_all[kWaves][kQT];
@@ -867,7 +871,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     if (ctr->abort) return;
     unsigned int *lst = lst_all[wave_id()];
     unsigned int *lstd = lstd_all[SEL ? wave_id() : 0];
-    unsigned int *qorig = qorig_all[SEL ? wave_id() : 0];
+    unsigned int *qrow_s = qrow_all[wave_id()];
+    unsigned int *qid = qid_all[wave_id()];
     unsigned int capped = 0;
     unsigned int *tpre = pre_all[wave_id()];
     unsigned int *tcnt = cnt_all[wave_id()];
@@ -921,6 +926,126 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned int cell0 = 0;
     unsigned int ev_end = 0;  // first row after the current event
     const uint2 *__restrict__ sid = reinterpret_cast<const uint2 *>(sorted_id);
+    // Queries take the wave's kQT list slots in turn (query number k of the wave
+    // uses slot k mod kQT).  First-stage survivors stay queued across tiles, and
+    // the lists of the pending queries are written out together: when the next
+    // group of queries would not find free slots (the queue is emptied first) and
+    // at the end of the share.  A tile of a sparse cell holds a few queries, so
+    // the queue's partial drain and the list stores are shared by many tiles.
+    unsigned int head = 0, tail = 0;     // queued survivors [head, tail)
+    unsigned int pend0 = 0, pend_n = 0;  // pending queries: numbers [pend0, pend0 + pend_n)
+    // A pair that passes the full test joins the list of the query in slot q.
+    auto keep = [&](bool pass, unsigned int q, unsigned int j, float D) {
+        if (pass) {
+            const unsigned int pos = atomicAdd(&qcnt[q], 1u);
+            if (pos < static_cast<unsigned int>(kListCap)) {
+                lst[q * kListCap + pos] = j;
+                if (SEL) lstd[q * kListCap + pos] = __float_as_uint(D);
+            }
+        }
+    };
+    // Second stage for ring entries [h, h + nb): lane l takes entry h + l and
+    // adds terms kLead.. of the definition to the first stage's partial sum, in
+    // the same order.  A row-addressed entry names its query's slot and its
+    // candidate row (the remaining coordinates are loaded); a lane-addressed entry
+    // (in the chunk loop) names the lane of the current chunk that holds the
+    // candidate.
+    auto finish_rows = [&](unsigned int h, unsigned int nb) {
+        wave_lds_sync();
+        const bool act = static_cast<unsigned int>(lane) < nb;
+        const unsigned int e = (h + lane) & (kRing - 1);
+        const unsigned long long ent = act ? ring[e] : 0ull;
+        const float a3 = act ? racc[e] : 0.0f;
+        const unsigned int q = static_cast<unsigned int>(ent >> 32);
+        const unsigned int s2 = static_cast<unsigned int>(ent);
+        const unsigned int qr = qrow_s[q];
+        const float *crow = sorted + static_cast<size_t>(s2) * DP;
+        float cc[DP];
+#pragma unroll
+        for (int k = kLead; k < DP; ++k) cc[k] = crow[k];
+        const unsigned int j2 = sorted_id[2u * s2];
+        const float D = add_terms<kLead, DP, DP>(a3, cc, sorted + static_cast<size_t>(qr) * DP);
+        keep(act && D < r2 && s2 != qr, q, j2, D);
+        wave_lds_sync();
+    };
+    // Empties the queue (row-addressed entries; lane-addressed ones never outlive
+    // their chunk).
+    auto drain_all = [&]() {
+        if constexpr (kRowRing) {
+            if (tail != head) {
+                finish_rows(head, tail - head);
+                head = tail;
+            }
+        }
+    };
+    // Writes out the lists of pending queries [f0, f0 + nf), nf <= kQT, whose
+    // survivors are all finished; lane l takes query f0 + l.  Kept counts for every
+    // query; lists that fit go to their fixed place (kListCap slots per original
+    // row) as found, in 16-byte pieces, and the placement pass orders every such
+    // list by neighbour id; the sorted rows of longer ones are queued (one atomic
+    // each) for the placement pass to collect again.  With the cap binding (SEL and
+    // more than K hits), the entries of those lists are numbered through a prefix
+    // over their lengths; each lane takes one entry, finds its query by binary
+    // search, ranks it by its (D, j) key within its list (D >= 0, so its bits order
+    // like the value; keys are distinct) and, if the rank is below K, writes it at
+    // that rank: the list's first K slots then hold its K nearest.  The stores are
+    // scattered, but everything about query i lands at places indexed by i, which
+    // the placement pass then reads in order.
+    auto flush = [&](unsigned int f0, unsigned int nf) {
+        wave_lds_sync();
+        const bool mine = static_cast<unsigned int>(lane) < nf;
+        const unsigned int sl = (f0 + static_cast<unsigned int>(lane)) & (kQT - 1);
+        const unsigned int cnt = mine ? qcnt[sl] : 0u;
+        const unsigned int iq = qid[sl];
+        const unsigned int Ku = static_cast<unsigned int>(K);
+        const bool fits = mine && cnt <= static_cast<unsigned int>(kListCap) && (SEL || cnt <= Ku);
+        if (mine) {
+            kept[iq] = min(cnt, Ku) | (fits ? 0u : kKeptLong);
+            if (cnt > Ku) ++capped;
+            if (!fits) long_slots[atomicAdd(&ctr->heavy_count, 1u)] = qrow_s[sl];
+        }
+        if (fits && !(SEL && cnt > Ku)) {
+            const uint4 *from = reinterpret_cast<const uint4 *>(lst + sl * kListCap);
+            uint4 *to = reinterpret_cast<uint4 *>(temp + static_cast<size_t>(iq) * kListCap);
+            for (unsigned int k = 0; 4u * k < cnt; ++k) to[k] = from[k];
+        }
+        if (SEL) {
+            const unsigned int take = fits && cnt > Ku ? cnt : 0u;
+            const unsigned int inc = wave_inclusive_scan(take);
+            const unsigned int T = __builtin_amdgcn_readlane(inc, 63);
+            if (mine) {
+                tpre[lane] = inc - take;
+                tcnt[lane] = take;
+            }
+            wave_lds_sync();
+            auto entry_query = [&](unsigned int t) {
+                int lo = 0, hi = static_cast<int>(nf) - 1;  // last query whose list starts at or before t
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (tpre[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                return lo;
+            };
+            for (unsigned int t0 = 0; t0 < T; t0 += 64) {
+                const unsigned int t = t0 + lane;
+                if (t < T) {
+                    const int lo = entry_query(t);
+                    const unsigned int ls = (f0 + static_cast<unsigned int>(lo)) & (kQT - 1);
+                    const unsigned int cq = tcnt[lo];
+                    const unsigned int *l = lst + ls * kListCap;
+                    const unsigned int *ld = lstd + ls * kListCap;
+                    const unsigned int x = t - tpre[lo];
+                    const unsigned long long key = (static_cast<unsigned long long>(ld[x]) << 32) | l[x];
+                    unsigned int sr = 0;  // the entry's rank by (D, j) in its list
+                    for (unsigned int u = 0; u < cq; ++u)
+                        sr += ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) < key ? 1u : 0u;
+                    if (sr < Ku) temp[static_cast<size_t>(qid[ls]) * kListCap + sr] = l[x];
+                }
+            }
+        }
+        wave_lds_sync();
+    };
     // The share is read in windows of 64 queries: lane l holds query win + l (its
     // original row and packed cell), and a tile is a run of consecutive lanes with the
     // same cell, found by a ballot (no per-tile lookup of where the cell ends).
@@ -973,7 +1098,25 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         else if (4u * left > share) __builtin_amdgcn_s_setprio(1);
                         else __builtin_amdgcn_s_setprio(0);
                     }
-                    if (lane < kQT) qcnt[lane] = 0u;
+                    // Slots for the group's queries; when they do not fit, the queue is
+                    // emptied and the pending lists written out first.
+                    if (pend_n + static_cast<unsigned int>(Qn) > static_cast<unsigned int>(kQT)) {
+                        drain_all();
+                        flush(pend0, pend_n);
+                        pend0 += pend_n;
+                        pend_n = 0;
+                    }
+                    const unsigned int gs = pend0 + pend_n;  // number of the group's first query
+                    // Original row of query q0 + lane, held by lane q0 + lane - win.
+                    const unsigned int iq = static_cast<unsigned int>(
+                        __shfl(static_cast<int>(v_orig), static_cast<int>((q0 - win + lane) & 63u)));
+                    if (lane < Qn) {
+                        const unsigned int sl = (gs + static_cast<unsigned int>(lane)) & (kQT - 1);
+                        qcnt[sl] = 0u;
+                        qrow_s[sl] = q0 + lane;
+                        qid[sl] = iq;
+                    }
+                    pend_n += static_cast<unsigned int>(Qn);
                     // Candidate rows are fetched one chunk ahead so that their latency
                     // overlaps the tests of the current chunk (with row-addressed ring entries
                     // only the leading coordinates, one 16-byte load).  Idle lanes read row 0
@@ -1009,40 +1152,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         // Lanes past the last candidate fail every first-stage test.
                         if (mm >= M) cn[0] = INFINITY;
                     };
-                    // A pair that passes the full test joins query q's list.
-                    auto keep = [&](bool pass, unsigned int q, unsigned int j, float D) {
-                        if (pass) {
-                            const unsigned int pos = atomicAdd(&qcnt[q], 1u);
-                            if (pos < static_cast<unsigned int>(kListCap)) {
-                                lst[q * kListCap + pos] = j;
-                                if (SEL) lstd[q * kListCap + pos] = __float_as_uint(D);
-                            }
-                        }
-                    };
-                    // Second stage for ring entries [h, h + nb): lane l takes entry h + l and
-                    // adds terms kLead.. of the definition to the first stage's partial sum,
-                    // in the same order.  A row-addressed entry names its candidate row (the
-                    // remaining coordinates are loaded); a lane-addressed entry (below) names
-                    // the lane of the current chunk that holds the candidate.
-                    auto finish_rows = [&](unsigned int h, unsigned int nb) {
-                        wave_lds_sync();
-                        const bool act = static_cast<unsigned int>(lane) < nb;
-                        const unsigned int e = (h + lane) & (kRing - 1);
-                        const unsigned long long ent = act ? ring[e] : 0ull;
-                        const float a3 = act ? racc[e] : 0.0f;
-                        const unsigned int q = static_cast<unsigned int>(ent >> 32);
-                        const unsigned int s2 = static_cast<unsigned int>(ent);
-                        const float *crow = sorted + static_cast<size_t>(s2) * DP;
-                        float cc[DP];
-    #pragma unroll
-                        for (int k = kLead; k < DP; ++k) cc[k] = crow[k];
-                        const unsigned int j2 = sorted_id[2u * s2];
-                        const float D = add_terms<kLead, DP, DP>(a3, cc, sorted + static_cast<size_t>(q0 + q) * DP);
-                        keep(act && D < r2 && s2 != q0 + q, q, j2, D);
-                        wave_lds_sync();
-                    };
                     fetch(0u);
-                    unsigned int head = 0, tail = 0;
                     for (unsigned int base = 0; base < M; base += 64) {
                         float c[kHeld];
     #pragma unroll
@@ -1068,9 +1178,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                 const unsigned int s2 = static_cast<unsigned int>(__shfl(static_cast<int>(s), cl));
                                 const unsigned int j2 = static_cast<unsigned int>(__shfl(static_cast<int>(jid), cl));
                                 const float part = __uint_as_float(static_cast<unsigned int>(ent));
+                                const unsigned int qr = qrow_s[q];
                                 const float D =
-                                    add_terms<kLead, DP, DP>(part, cc, sorted + static_cast<size_t>(q0 + q) * DP);
-                                keep(act && D < r2 && s2 != q0 + q, q, j2, D);
+                                    add_terms<kLead, DP, DP>(part, cc, sorted + static_cast<size_t>(qr) * DP);
+                                keep(act && D < r2 && s2 != qr, q, j2, D);
                                 wave_lds_sync();
                             }
                         };
@@ -1095,12 +1206,12 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                             if (acc < r2) {
                                 ++survived;
                                 const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
+                                const unsigned int slot = uniform((gs + static_cast<unsigned int>(q)) & (kQT - 1));
                                 if constexpr (kRowRing) {
-                                    const unsigned int qu = uniform(static_cast<unsigned int>(q));
-                                    ring[e] = (static_cast<unsigned long long>(qu) << 32) | s;
+                                    ring[e] = (static_cast<unsigned long long>(slot) << 32) | s;
                                     racc[e] = acc;
                                 } else {
-                                    ring[e] = (static_cast<unsigned long long>((static_cast<unsigned int>(q) << 6) |
+                                    ring[e] = (static_cast<unsigned long long>((slot << 6) |
                                                                               static_cast<unsigned int>(lane)) << 32) |
                                               __float_as_uint(acc);
                                 }
@@ -1117,80 +1228,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                             head = tail;
                         }
                     }
-                    if constexpr (kRowRing) {
-                        if (tail != head) finish_rows(head, tail - head);
-                    }
-                    const unsigned int cnt = lane < Qn ? qcnt[lane] : 0u;  // hits of query q0 + lane
                     if (lane < Qn) tested += M;
-                    // Original row of query q0 + lane, held by lane q0 + lane - win.
-                    const unsigned int iq = static_cast<unsigned int>(
-                        __shfl(static_cast<int>(v_orig), static_cast<int>((q0 - win + lane) & 63u)));
-                    wave_lds_sync();
-                    // Kept counts for every query; lists that fit are stored at a fixed place
-                    // (kListCap slots per original row); the sorted rows of longer ones are
-                    // queued (one atomic each) for the placement pass to collect again.
-                    const bool fits = lane < Qn && cnt <= static_cast<unsigned int>(kListCap) &&
-                                      (SEL || cnt <= static_cast<unsigned int>(K));
-                    if (lane < Qn) {
-                        const unsigned int i = iq;
-                        // Scattered stores (the count, then the list in 16-byte pieces) put
-                        // everything about query i at places indexed by i, which the placement
-                        // pass then reads in order.
-                        const unsigned int kq = min(cnt, static_cast<unsigned int>(K));
-                        kept[i] = kq | (fits ? 0u : kKeptLong);
-                        if (cnt > static_cast<unsigned int>(K)) ++capped;
-                        if (!fits) long_slots[atomicAdd(&ctr->heavy_count, 1u)] = q0 + lane;
-                    }
-                    // Lists that fit go to their fixed place (kListCap slots per original row)
-                    // as found, in 16-byte pieces; the placement pass orders every such list
-                    // by neighbour id.  With the cap binding (SEL and more than K hits), the
-                    // entries of those lists are numbered through a prefix over their
-                    // lengths; each lane takes one entry, finds its query by binary search,
-                    // ranks it by its (D, j) key within its list (D >= 0, so its bits order
-                    // like the value; keys are distinct) and, if the rank is below K, writes
-                    // it at that rank: the list's first K slots then hold its K nearest.
-                    const unsigned int Ku = static_cast<unsigned int>(K);
-                    if (fits && !(SEL && cnt > Ku)) {
-                        const uint4 *from = reinterpret_cast<const uint4 *>(lst + lane * kListCap);
-                        uint4 *to = reinterpret_cast<uint4 *>(temp + static_cast<size_t>(iq) * kListCap);
-                        for (unsigned int k = 0; 4u * k < cnt; ++k) to[k] = from[k];
-                    }
-                    if (SEL) {
-                        const unsigned int take = fits && cnt > Ku ? cnt : 0u;
-                        const unsigned int inc = wave_inclusive_scan(take);
-                        const unsigned int T = __builtin_amdgcn_readlane(inc, 63);
-                        if (lane < Qn) {
-                            tpre[lane] = inc - take;
-                            tcnt[lane] = take;
-                            qorig[lane] = iq;
-                        }
-                        wave_lds_sync();
-                        auto entry_query = [&](unsigned int t) {
-                            int lo = 0, hi = Qn - 1;  // last query whose list starts at or before t
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (tpre[mid] <= t) lo = mid;
-                                else hi = mid - 1;
-                            }
-                            return lo;
-                        };
-                        for (unsigned int t0 = 0; t0 < T; t0 += 64) {
-                            const unsigned int t = t0 + lane;
-                            if (t < T) {
-                                const int lo = entry_query(t);
-                                const unsigned int cq = tcnt[lo];
-                                const unsigned int *l = lst + lo * kListCap;
-                                const unsigned int *ld = lstd + lo * kListCap;
-                                const unsigned int x = t - tpre[lo];
-                                const unsigned long long key = (static_cast<unsigned long long>(ld[x]) << 32) | l[x];
-                                unsigned int sr = 0;  // the entry's rank by (D, j) in its list
-                                for (unsigned int u = 0; u < cq; ++u)
-                                    sr += ((static_cast<unsigned long long>(ld[u]) << 32) | l[u]) < key ? 1u : 0u;
-                                if (sr < Ku) temp[static_cast<size_t>(qorig[lo]) * kListCap + sr] = l[x];
-                            }
-                        }
-                    }
-                    wave_lds_sync();
                 }
                 t0 = t1;
             }
@@ -1198,6 +1236,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
         }
         piece = kPieces > 1 ? x_dyn + pool + __builtin_amdgcn_readfirstlane(claimed) * pools : x_end;
     }
+    drain_all();
+    if (pend_n) flush(pend0, pend_n);
     capped = wave_sum(capped);
     tested = wave_sum(tested);
     survived = wave_sum(survived);
