@@ -824,12 +824,21 @@ __device__ __forceinline__ unsigned int wave_runs(const int (&u)[kMaxAxes], unsi
 
 // ------------------------------------------------------------------ search
 
-// Waves per SIMD the search asks the register allocator for: rows of up to 8
-// floats fit in 64 registers (8 waves); 12-float rows run 6 waves without spills
-// (asked for 7 they spill, and the search on 300k 12-D points took 138 us against
-// 131; 8 waves 166 us); wider rows keep the compiler's choice (no spills).
+// Row-addressed ring entries (the entry names the candidate's sorted row and the
+// remaining coordinates are loaded when the entry is finished) for rows of up to
+// 12 floats: a lane then holds only a candidate's first four coordinates.  Wider
+// rows keep the whole candidate row in registers and exchange coordinates between
+// lanes instead.  On the 300k-point 12-D event row-addressed entries took the
+// search from 115.5 to 109.2 us at 6 waves per SIMD, and the registers they free
+// allow 8 waves: 89.3 us (7 waves: 101.5 us).
 template <int DP>
-constexpr int kSearchWaves = DP <= 8 ? 8 : (DP <= 12 ? 6 : 1);
+constexpr bool kRowRingFor = DP <= 12;
+
+// Waves per SIMD the search asks the register allocator for: with row-addressed
+// entries rows of up to 12 floats fit in 64 registers (8 waves, some scalar
+// registers spilled to vector lanes); wider rows keep the compiler's choice.
+template <int DP>
+constexpr int kSearchWaves = kRowRingFor<DP> ? 8 : 1;
 
 // SEL: the cap K is below kListCap, so a list that fits may still need the K
 // nearest of its hits: the lists then also hold each hit's distance.
@@ -863,7 +872,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     // Row-addressed entries: q << 32 | candidate row, with the partial sum in racc;
     // lane-addressed entries: (q << 6 | lane) << 32 | bits of the partial sum.
     __shared__ unsigned long long ring_all[kWaves][kRing];
-    __shared__ float racc_all[DP <= 8 ? kWaves : 1][DP <= 8 ? kRing : 1];
+    __shared__ float racc_all[kRowRingFor<DP> ? kWaves : 1][kRowRingFor<DP> ? kRing : 1];
     __shared__ unsigned int mark_all[kWaves][64];  // run starting at each lane of a chunk, plus one
     __shared__ unsigned long long tested_w[kWaves];
     __shared__ unsigned long long survived_w[kWaves];
@@ -878,19 +887,16 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned int *tcnt = cnt_all[wave_id()];
     unsigned int *qcnt = qcnt_all[wave_id()];
     unsigned long long *ring = ring_all[wave_id()];
-    float *racc = racc_all[DP <= 8 ? wave_id() : 0];
+    float *racc = racc_all[kRowRingFor<DP> ? wave_id() : 0];
     unsigned int *mark = mark_all[wave_id()];
     const int lane = lane_id();
-    // Terms before the first exact rejection test: two for rows of up to 8 floats
-    // (their three-term test rejects few more pairs than two terms do, and the
-    // first stage runs for every query and candidate), four for 12-float rows
-    // (fewer survivors for the lane exchange of the second stage), three for
-    // wider rows.
-    constexpr int kLead = DP <= 8 ? 2 : (DP <= 12 ? 4 : 3);
-    // Row-addressed ring entries (the entry names the candidate's sorted row and the
-    // remaining coordinates are loaded when the entry is finished) for rows of up to
-    // 8 floats; wider rows exchange the candidate's coordinates between lanes instead.
-    constexpr bool kRowRing = DP <= 8;
+    // Terms before the first exact rejection test: two for rows of up to 12 floats
+    // (a three-term test rejects few more pairs than two terms do, and the first
+    // stage runs for every query and candidate; on the 300k-point 12-D event two,
+    // three and four terms took 87.5, 88.7 and 89.6 us), three for wider rows
+    // (fewer survivors for the lane exchange of the second stage).
+    constexpr int kLead = DP <= 12 ? 2 : 3;
+    constexpr bool kRowRing = kRowRingFor<DP>;
     // Pairs examined (lane q counts those of query q of each group) and pairs that
     // reached the second stage (each lane counts those it queued).  Per-lane counts
     // in vector registers, summed once at the end: scalar registers are the scarce
@@ -898,9 +904,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned long long tested = 0;
     unsigned long long survived = 0;
 
-    // The cell scan cuts the queries, in cell order, into kPieces pieces of equal
-    // work per wave (one for rows of up to 8 floats, two for wider ones) (its cells' fixed costs plus its queries; a piece may start or
-    // end inside a cell, so a dense cell is split instead of holding up one wave).
+    // The cell scan cuts the queries, in cell order, into kPieces pieces per wave
+    // (one for rows of up to 12 floats, two for wider ones) of equal work (its
+    // cells' fixed costs plus its queries; a piece may start or end inside a cell,
+    // so a dense cell is split instead of holding up one wave).
     // Workgroups are dealt to the 8 XCDs round-robin; the workgroups of one XCD
     // take a contiguous share of the pieces, so that they share their rows in its
     // L2: each wave first takes one piece of the share, then claims the share's
