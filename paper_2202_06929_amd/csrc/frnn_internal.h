@@ -31,15 +31,15 @@ constexpr unsigned int kTileWeight = 4;
 // The search's queries are cut into search_pieces(DP) pieces of equal work per
 // wave: each wave takes one piece of its XCD's share, then claims the share's
 // other pieces one at a time from kPools counters per XCD, so that waves that
-// finish early take work from the others.  Rows of up to 12 floats keep one piece
+// finish early take work from the others.  Rows of up to 24 floats keep one piece
 // per wave: their queries cost about the same, and the claims and the cells cut
 // twice cost more than they even out (the 120k-point 8-D search took 34.9 us with
-// two pieces against 30.9 with one; the 300k-point 12-D search 89.6 against 88.0).
-// Wider rows, whose candidate rows stay in registers and whose queries cost more,
-// take two (two pieces took the 12-D search from 118.5 to 114.5 us when its rows
-// were held that way).
+// two pieces against 30.9 with one; whole 120k-point builds with 16- and 24-float
+// rows 0.089 and 0.120 ms against 0.085 and 0.117).  Wider rows, whose queries
+// cost more and which run fewer waves per SIMD, take two (32-, 48- and 64-float
+// rows: 0.173, 0.292 and 0.558 ms against 0.181, 0.340 and 0.713 with one).
 constexpr int kMaxPieces = 2;
-constexpr int search_pieces(int dpad) { return dpad <= 12 ? 1 : 2; }
+constexpr int search_pieces(int dpad) { return dpad <= 24 ? 1 : 2; }
 constexpr int kPools = 8;
 constexpr int kPoolStride = 32;  // counters 128 bytes apart
 constexpr int kKeysBlock = 1024;     // threads per workgroup of the key/histogram pass

@@ -12,11 +12,10 @@
 //   k_search      each wave takes a share of equal work in cell order: a
 //                 cell's queries against the (2R+1)^(axes-1) contiguous runs of
 //                 neighbouring cells along axis 0; each lane holds one candidate (its
-//                 leading coordinates, or its whole row for rows wider than 8
-//                 floats), query rows are wave-uniform; an exact early exit after the
-//                 first two to four terms of the distance sum; ballots queue the
-//                 survivors, whose sums are finished 64 at a time; each list is
-//                 stored as found
+//                 first four coordinates), query rows are wave-uniform; an exact
+//                 early exit after the first two or three terms of the distance
+//                 sum; ballots queue the survivors, whose sums are finished 64 at a
+//                 time; the lists of pending queries are stored as found, in batches
 //   k_kept_sums   kept totals per placement tile and per group of tiles
 //   k_place       output offsets from the totals and a block scan; each short list
 //                 sorted by its query's thread and the block's output formed in LDS,
@@ -824,21 +823,12 @@ __device__ __forceinline__ unsigned int wave_runs(const int (&u)[kMaxAxes], unsi
 
 // ------------------------------------------------------------------ search
 
-// Row-addressed ring entries (the entry names the candidate's sorted row and the
-// remaining coordinates are loaded when the entry is finished) for rows of up to
-// 12 floats: a lane then holds only a candidate's first four coordinates.  Wider
-// rows keep the whole candidate row in registers and exchange coordinates between
-// lanes instead.  On the 300k-point 12-D event row-addressed entries took the
-// search from 115.5 to 109.2 us at 6 waves per SIMD, and the registers they free
-// allow 8 waves: 89.3 us (7 waves: 101.5 us).
+// Waves per SIMD the search asks the register allocator for: a lane holds only a
+// candidate's first four coordinates, so rows of up to 16 floats fit in 64
+// registers (8 waves, some scalar registers spilled to vector lanes); wider rows,
+// whose second stage holds the rest of a row, keep the compiler's choice.
 template <int DP>
-constexpr bool kRowRingFor = DP <= 12;
-
-// Waves per SIMD the search asks the register allocator for: with row-addressed
-// entries rows of up to 12 floats fit in 64 registers (8 waves, some scalar
-// registers spilled to vector lanes); wider rows keep the compiler's choice.
-template <int DP>
-constexpr int kSearchWaves = kRowRingFor<DP> ? 8 : 1;
+constexpr int kSearchWaves = DP <= 16 ? 8 : 1;
 
 // SEL: the cap K is below kListCap, so a list that fits may still need the K
 // nearest of its hits: the lists then also hold each hit's distance.
@@ -869,10 +859,10 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     __shared__ unsigned int pre_all[kWaves][kQT + 1];
     __shared__ unsigned int cnt_all[kWaves][kQT];
     __shared__ unsigned int qcnt_all[kWaves][kQT];
-    // Row-addressed entries: q << 32 | candidate row, with the partial sum in racc;
-    // lane-addressed entries: (q << 6 | lane) << 32 | bits of the partial sum.
+    // Queued first-stage survivors: query slot << 32 | candidate's sorted row, with
+    // the partial sum in racc.
     __shared__ unsigned long long ring_all[kWaves][kRing];
-    __shared__ float racc_all[kRowRingFor<DP> ? kWaves : 1][kRowRingFor<DP> ? kRing : 1];
+    __shared__ float racc_all[kWaves][kRing];
     __shared__ unsigned int mark_all[kWaves][64];  // run starting at each lane of a chunk, plus one
     __shared__ unsigned long long tested_w[kWaves];
     __shared__ unsigned long long survived_w[kWaves];
@@ -887,16 +877,16 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned int *tcnt = cnt_all[wave_id()];
     unsigned int *qcnt = qcnt_all[wave_id()];
     unsigned long long *ring = ring_all[wave_id()];
-    float *racc = racc_all[kRowRingFor<DP> ? wave_id() : 0];
+    float *racc = racc_all[wave_id()];
     unsigned int *mark = mark_all[wave_id()];
     const int lane = lane_id();
     // Terms before the first exact rejection test: two for rows of up to 12 floats
     // (a three-term test rejects few more pairs than two terms do, and the first
     // stage runs for every query and candidate; on the 300k-point 12-D event two,
-    // three and four terms took 87.5, 88.7 and 89.6 us), three for wider rows
-    // (fewer survivors for the lane exchange of the second stage).
+    // three and four terms took 87.5, 88.7 and 89.6 us), three for wider rows (two
+    // terms took whole 120k-point builds with 32-, 48- and 64-float rows from
+    // 0.173, 0.292 and 0.558 ms to 0.204, 0.423 and 1.126 ms).
     constexpr int kLead = DP <= 12 ? 2 : 3;
-    constexpr bool kRowRing = kRowRingFor<DP>;
     // Pairs examined (lane q counts those of query q of each group) and pairs that
     // reached the second stage (each lane counts those it queued).  Per-lane counts
     // in vector registers, summed once at the end: scalar registers are the scarce
@@ -905,7 +895,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     unsigned long long survived = 0;
 
     // The cell scan cuts the queries, in cell order, into kPieces pieces per wave
-    // (one for rows of up to 12 floats, two for wider ones) of equal work (its
+    // (one for rows of up to 24 floats, two for wider ones) of equal work (its
     // cells' fixed costs plus its queries; a piece may start or end inside a cell,
     // so a dense cell is split instead of holding up one wave).
     // Workgroups are dealt to the 8 XCDs round-robin; the workgroups of one XCD
@@ -953,10 +943,9 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
     };
     // Second stage for ring entries [h, h + nb): lane l takes entry h + l and
     // adds terms kLead.. of the definition to the first stage's partial sum, in
-    // the same order.  A row-addressed entry names its query's slot and its
-    // candidate row (the remaining coordinates are loaded); a lane-addressed entry
-    // (in the chunk loop) names the lane of the current chunk that holds the
-    // candidate.
+    // the same order.  An entry names its query's slot and the candidate's sorted
+    // row; the remaining coordinates are loaded here (the chunk holds only the
+    // first four), so entries outlive their chunk and tile.
     auto finish_rows = [&](unsigned int h, unsigned int nb) {
         wave_lds_sync();
         const bool act = static_cast<unsigned int>(lane) < nb;
@@ -975,14 +964,11 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
         keep(act && D < r2 && s2 != qr, q, j2, D);
         wave_lds_sync();
     };
-    // Empties the queue (row-addressed entries; lane-addressed ones never outlive
-    // their chunk).
+    // Empties the queue.
     auto drain_all = [&]() {
-        if constexpr (kRowRing) {
-            if (tail != head) {
-                finish_rows(head, tail - head);
-                head = tail;
-            }
+        if (tail != head) {
+            finish_rows(head, tail - head);
+            head = tail;
         }
     };
     // Writes out the lists of pending queries [f0, f0 + nf), nf <= kQT, whose
@@ -1124,13 +1110,14 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         qid[sl] = iq;
                     }
                     pend_n += static_cast<unsigned int>(Qn);
-                    // Candidate rows are fetched one chunk ahead so that their latency
-                    // overlaps the tests of the current chunk (with row-addressed ring entries
-                    // only the leading coordinates, one 16-byte load).  Idle lanes read row 0
-                    // (any row is a valid address) and are masked out of every ballot.
-                    constexpr int kHeld = kRowRing ? 4 : DP;  // candidate coordinates held per lane
+                    // Candidates are fetched one chunk ahead so that their latency overlaps
+                    // the tests of the current chunk: each lane holds its candidate's first
+                    // four coordinates (one 16-byte load).  Idle lanes read row 0 (any row
+                    // is a valid address) and are masked out of every ballot.
+                    constexpr int kHeld = 4;  // candidate coordinates held per lane
+                    static_assert(kLead <= kHeld, "the first stage uses the held coordinates");
                     float cn[kHeld];
-                    unsigned int sn, jn = 0u;
+                    unsigned int sn;
                     // Candidate b + lane lies in the last run that starts at or before it:
                     // each run that starts inside the chunk marks its first lane (the run
                     // holding candidate b marks lane 0) and a prefix maximum spreads the
@@ -1146,16 +1133,11 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         const unsigned int srow = static_cast<unsigned int>(__shfl(start, r)) +
                                                   (mm - static_cast<unsigned int>(__shfl(pre, r)));
                         sn = mm < M ? srow : 0u;
-                        if constexpr (kRowRing) {
-                            const float4 v = *reinterpret_cast<const float4 *>(sorted + static_cast<size_t>(sn) * DP);
-                            cn[0] = v.x;
-                            cn[1] = v.y;
-                            cn[2] = v.z;
-                            cn[3] = v.w;
-                        } else {
-                            load_row<DP>(sorted, sn, cn);
-                            jn = sorted_id[2u * sn];
-                        }
+                        const float4 v = *reinterpret_cast<const float4 *>(sorted + static_cast<size_t>(sn) * DP);
+                        cn[0] = v.x;
+                        cn[1] = v.y;
+                        cn[2] = v.z;
+                        cn[3] = v.w;
                         // Lanes past the last candidate fail every first-stage test.
                         if (mm >= M) cn[0] = INFINITY;
                     };
@@ -1164,34 +1146,8 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         float c[kHeld];
     #pragma unroll
                         for (int k = 0; k < kHeld; ++k) c[k] = cn[k];
-                        const unsigned int s = sn, jid = jn;
+                        const unsigned int s = sn;
                         if (base + 64 < M) fetch(base + 64);
-                        // Lane-addressed entries: the candidate's coordinates are exchanged
-                        // between lanes of the current chunk.
-                        auto finish = [&](unsigned int h, unsigned int nb) {
-                            if constexpr (kRowRing) {
-                                finish_rows(h, nb);
-                            } else {
-                                wave_lds_sync();
-                                const bool act = static_cast<unsigned int>(lane) < nb;
-                                const unsigned int e = (h + lane) & (kRing - 1);
-                                const unsigned long long ent = act ? ring[e] : 0ull;
-                                float cc[DP];
-                                const unsigned int code = static_cast<unsigned int>(ent >> 32);
-                                const int cl = static_cast<int>(code & 63u);
-                                const unsigned int q = code >> 6;
-    #pragma unroll
-                                for (int k = kLead; k < DP; ++k) cc[k] = __shfl(c[k], cl);
-                                const unsigned int s2 = static_cast<unsigned int>(__shfl(static_cast<int>(s), cl));
-                                const unsigned int j2 = static_cast<unsigned int>(__shfl(static_cast<int>(jid), cl));
-                                const float part = __uint_as_float(static_cast<unsigned int>(ent));
-                                const unsigned int qr = qrow_s[q];
-                                const float D =
-                                    add_terms<kLead, DP, DP>(part, cc, sorted + static_cast<size_t>(qr) * DP);
-                                keep(act && D < r2 && s2 != qr, q, j2, D);
-                                wave_lds_sync();
-                            }
-                        };
                         // Query rows are wave-uniform (scalar loads); the next one is
                         // requested before the current one is tested (the sorted rows end with
                         // one padding row, so the request after the last query stays in bounds).
@@ -1214,25 +1170,14 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                                 ++survived;
                                 const unsigned int e = (tail + prefix_count(m1)) & (kRing - 1);
                                 const unsigned int slot = uniform((gs + static_cast<unsigned int>(q)) & (kQT - 1));
-                                if constexpr (kRowRing) {
-                                    ring[e] = (static_cast<unsigned long long>(slot) << 32) | s;
-                                    racc[e] = acc;
-                                } else {
-                                    ring[e] = (static_cast<unsigned long long>((slot << 6) |
-                                                                              static_cast<unsigned int>(lane)) << 32) |
-                                              __float_as_uint(acc);
-                                }
+                                ring[e] = (static_cast<unsigned long long>(slot) << 32) | s;
+                                racc[e] = acc;
                             }
                             tail += static_cast<unsigned int>(__popcll(m1));
                             if (tail - head >= 64u) {
-                                finish(head, 64u);
+                                finish_rows(head, 64u);
                                 head += 64u;
                             }
-                        }
-                        // Lane-addressed entries refer to this chunk's registers: drain them now.
-                        if (!kRowRing && tail != head) {
-                            finish(head, tail - head);
-                            head = tail;
                         }
                     }
                     if (lane < Qn) tested += M;
