@@ -1144,7 +1144,7 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                     fetch(0u);
                     for (unsigned int base = 0; base < M; base += 64) {
                         float c[kHeld];
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < kHeld; ++k) c[k] = cn[k];
                         const unsigned int s = sn;
                         if (base + 64 < M) fetch(base + 64);
@@ -1152,14 +1152,14 @@ __global__ __launch_bounds__(kBlock, kSearchWaves<DP>) void k_search(const float
                         // requested before the current one is tested (the sorted rows end with
                         // one padding row, so the request after the last query stays in bounds).
                         float qn[kLead];
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < kLead; ++k) qn[k] = sorted[static_cast<size_t>(q0) * DP + k];
                         const float *qrow = sorted + static_cast<size_t>(q0) * DP;
                         for (int q = 0; q < Qn; ++q, qrow += DP) {
                             float qc[kLead];
-    #pragma unroll
+#pragma unroll
                             for (int k = 0; k < kLead; ++k) qc[k] = qn[k];
-    #pragma unroll
+#pragma unroll
                             for (int k = 0; k < kLead; ++k) qn[k] = qrow[DP + k];
                             // First stage: kLead terms for all 64 candidates; pairs that are not
                             // yet at r2 are queued (exact: the remaining terms only add).
